@@ -1,0 +1,200 @@
+/*
+ * subquad.h -- C ABI of the SubQuad hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for a batch of immune-receptor sequences, the candidate-pair
+ * affinity stage of SubQuad (arXiv 2602.17330): MinHash sketches, an LSH index that
+ * yields the candidate list, a local-alignment channel on every candidate pair and the
+ * per-pair gated fusion of that channel with an embedding-cosine channel, forward and
+ * backward.  The paper's problem statement (Sec. 3.1) maps sequences to a sparse weighted
+ * graph; this library stops at the sparse list of fused pair affinities that populates it
+ * (Algorithm 1, preprocessing and affinity computation).
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is DEVICE memory on the current HIP device unless it is marked
+ *     "host".  The caller owns all memory and the library keeps no state between calls.
+ *     Entry points that take a workspace allocate nothing; subquad_check_seqs and
+ *     subquad_align_batch (the variant without a workspace) take a small stream-ordered
+ *     allocation (hipMallocAsync) and release it before returning.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it and the
+ *     call returns without waiting, except where a host output is documented.
+ *   - Sequences are rows of `stride` bytes: residue codes 0..19 in the order
+ *     ACDEFGHIKLMNPQRSTVWY, any value past the row's length (pad 0xFF by convention).
+ *     `lens[i]` is the length of row i.
+ *   - Return value: SUBQUAD_OK or one of the error codes below.  Arguments are validated on
+ *     the host before anything is enqueued; on an error nothing is enqueued and
+ *     subquad_last_error() describes it (thread-local, valid until the next call on the
+ *     same thread).  Device contents (residue codes, lengths) are validated only by
+ *     subquad_check_seqs; other kernels clamp out-of-range codes so that bad data can give
+ *     wrong results but never an out-of-bounds access.
+ */
+#ifndef SUBQUAD_H
+#define SUBQUAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum subquad_status {
+    SUBQUAD_OK = 0,
+    SUBQUAD_ERR_ARG = 1,        /* null pointer, negative or out-of-range size or parameter  */
+    SUBQUAD_ERR_RESIDUE = 2,    /* a residue code >= 20 within a sequence's length           */
+    SUBQUAD_ERR_LENGTH = 3,     /* a length below k or above stride                          */
+    SUBQUAD_ERR_CAPACITY = 4,   /* more candidate pairs than the output capacity             */
+    SUBQUAD_ERR_WORKSPACE = 5,  /* workspace smaller than the size function returns          */
+    SUBQUAD_ERR_HIP = 6         /* the HIP runtime reported an error                         */
+};
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *subquad_last_error(void);
+
+/* Library version string. */
+const char *subquad_version(void);
+
+/*
+ * subquad_check_seqs -- validate a sequence batch (Algorithm 1, preprocessing: the padded
+ * sequence rows every later stage reads).
+ *   seqs [n][stride] u8, lens [n] i32: the batch.  k: shingle length (1..5).
+ *   n_bad (host, may be NULL): receives the number of rows that fail.
+ * Synchronises `stream`.  Returns SUBQUAD_ERR_LENGTH if some k <= lens[i] <= stride fails,
+ * else SUBQUAD_ERR_RESIDUE if some code within a length is >= 20, else SUBQUAD_OK.
+ */
+int subquad_check_seqs(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                       int32_t k, int64_t *n_bad, void *stream);
+
+/*
+ * subquad_minhash -- MinHash sketch of every sequence (Algorithm 1, preprocessing; sketch
+ * size M as in Sec. 4.1 and the sampling-error bound of Appendix B).
+ *   sig [n][M] u64, row-major (out): sig[i][t] = min over the set of distinct k-mers x of
+ *   row i of h_t(x), with simple tabulation h_t(x) = XOR_p T[t][p][x_p] and the 20*k*M table
+ *   words T taken, in the order t, p, residue, from the SplitMix64 sequence started at
+ *   `seed`.  Requires k == 3 (the hot path's shingle length), 1 <= M <= 256, 3 <= stride
+ *   <= 64, stride % 4 == 0.  Row lengths must lie in [k, stride] (subquad_check_seqs).
+ */
+int subquad_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                    int32_t k, int32_t M, uint64_t seed, uint64_t *sig, void *stream);
+
+/*
+ * subquad_lsh_workspace_bytes -- bytes of device workspace subquad_lsh_candidates needs
+ * for n sequences, b bands and an output capacity of `cap` pairs.  Returns 0 if the sizes
+ * are out of range (n * b >= 2^32, cap < 0).
+ */
+size_t subquad_lsh_workspace_bytes(int64_t n, int32_t b, int64_t cap);
+
+/*
+ * subquad_lsh_candidates -- candidate list CAND of the MinHash LSH index (Algorithm 1,
+ * preprocessing; index of Sec. 4.2; cost O(|C|) + O(n log n), Appendix B).
+ *   sig [n][M] u64: signatures from subquad_minhash.  b bands of r rows, b * r <= M; band
+ *   beta covers signature rows beta*r .. beta*r + r - 1.
+ *   rep_offsets [R+1] i64 (may be NULL, then R must be 1): repertoire r is rows
+ *   rep_offsets[r] .. rep_offsets[r+1]-1; rep_offsets[0] = 0, rep_offsets[R] = n, ascending.
+ *   ws / ws_bytes: workspace of at least subquad_lsh_workspace_bytes(n, b, cap) bytes,
+ *   256-byte aligned.
+ *   pairs [cap][2] i32 (out): the pairs (i, j), i < j, of rows of one repertoire whose
+ *   r-tuples are exactly equal in at least one band; each pair once, sorted by (i, j).
+ *   row_offsets [n+1] i64 (out, may be NULL): CSR offsets into `pairs` by first index.
+ *   n_pairs (host out): the number of candidate pairs P.
+ * Synchronises `stream` once (to read P).  If P > cap, returns SUBQUAD_ERR_CAPACITY with
+ * *n_pairs = P; then `pairs` and `row_offsets` are unspecified and the call can be repeated
+ * with a larger capacity.
+ */
+int subquad_lsh_candidates(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r,
+                           const int64_t *rep_offsets, int64_t R, void *ws, size_t ws_bytes,
+                           int32_t *pairs, int64_t *row_offsets, int64_t cap,
+                           int64_t *n_pairs, void *stream);
+
+/*
+ * subquad_lsh_candidates_async -- as subquad_lsh_candidates, but never synchronises, so it
+ * can be captured in a HIP graph.  n_pairs_dev (device out, i64): P.  status_dev (device
+ * out, i32): 0, or SUBQUAD_ERR_CAPACITY when P > cap (then pairs and row_offsets are
+ * unspecified).  The sort is sized for `cap` pairs, so cap should be a tight bound.
+ */
+int subquad_lsh_candidates_async(const uint64_t *sig, int64_t n, int32_t M, int32_t b,
+                                 int32_t r, const int64_t *rep_offsets, int64_t R, void *ws,
+                                 size_t ws_bytes, int32_t *pairs, int64_t *row_offsets,
+                                 int64_t cap, int64_t *n_pairs_dev, int32_t *status_dev,
+                                 void *stream);
+
+/*
+ * subquad_self_scores -- self[i] = sum over x < lens[i] of subst[a_x][a_x], the local
+ * alignment score of a sequence with itself whenever every off-diagonal entry of subst is
+ * below every diagonal entry (as for BLOSUM62).  Used to normalise the alignment channel.
+ *   subst [20][20] i8, rows and columns in residue-code order.
+ */
+int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                        const int8_t *subst, int32_t *self, void *stream);
+
+/*
+ * subquad_align_batch -- local alignment channel on every candidate pair (Algorithm 1,
+ * affinity computation: the alignment affinity a^(1) of Eq. (afused)).  The paper's own
+ * kernel is a global edit distance (Appendix F.3); this channel is the Smith-Waterman local
+ * alignment score with Gotoh's affine gaps:
+ *   H = max(0, H_diag + subst[a_x][b_y], E, F), E = max(E_left - gap_extend,
+ *   H_left - gap_open), F = max(F_up - gap_extend, H_up - gap_open); score = max H,
+ * so a gap of length k costs gap_open + (k - 1) * gap_extend.
+ *   pairs [P][2] i32 (rows of seqs, any order, i == j allowed), scores [P] i32 (out).
+ *   gap_open, gap_extend: positive costs, 0 <= gap_extend <= gap_open <= 1000.
+ *   subst must be symmetric (as BLOSUM and PAM matrices are): each pair is aligned with its
+ *   shorter sequence as the first operand.  Requires stride % 4 == 0, 4 <= stride <= 64.
+ */
+int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                        const int32_t *pairs, int64_t P, const int8_t *subst,
+                        int32_t gap_open, int32_t gap_extend, int32_t *scores, void *stream);
+
+/*
+ * subquad_align_batch_ws -- as subquad_align_batch, with caller-provided scratch for the
+ * length sort that groups pairs of similar lengths into the same wavefront.
+ *   ws / ws_bytes: at least subquad_align_workspace_bytes(P) bytes, 4-byte aligned.
+ */
+size_t subquad_align_workspace_bytes(int64_t P);
+int subquad_align_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                           const int32_t *pairs, int64_t P, const int8_t *subst,
+                           int32_t gap_open, int32_t gap_extend, int32_t *scores, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/*
+ * subquad_gate_fwd -- per-pair dynamic affinity fusion, Sec. 3.6, Eq. (wm) and (afused),
+ * with the sigmoid channel weight of Eq. (alpha).  For pair p = (i, j):
+ *   s = align[p] / sqrt(self[i] * self[j])      (alignment channel)
+ *   c = <e_i, e_j> / (|e_i| |e_j|)               (embedding channel; 0 if a norm is 0)
+ *   x = (s, c, |lens[i] - lens[j]|, [vgene[i] == vgene[j]])
+ *   g = sigmoid(w2 . relu(W1 x + b1) + b2)       (= softmax weight of channel 1 over the
+ *                                                  channel logits (u, 0))
+ *   fused[p] = g * s + (1 - g) * c
+ *   emb [n][d] f32 row-major, d % 4 == 0, 4 <= d <= 1024.  self [n] i32 (> 0).
+ *   W1 [H][4], b1 [H], w2 [H], b2 [1] f32; H % 16 == 0, 16 <= H <= 256.
+ *   fused [P] f32 (out); gate [P] f32 (out, may be NULL): g.
+ */
+int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                     const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                     const int32_t *align, int64_t P, const float *W1, const float *b1,
+                     const float *w2, const float *b2, int32_t H, float *fused, float *gate,
+                     void *stream);
+
+/* Bytes of device workspace subquad_gate_bwd needs for H hidden units. */
+size_t subquad_gate_bwd_workspace_bytes(int32_t H);
+
+/*
+ * subquad_gate_bwd -- gradient of L = sum_p grad_fused[p] * fused[p] (the backward of
+ * subquad_gate_fwd, same arguments), recomputing every per-pair intermediate instead of
+ * storing it.  Gradients ACCUMULATE into the outputs (zero them first for a plain
+ * gradient): dW1 [H][4], db1 [H], dw2 [H], db2 [1], demb [n][d] (may be NULL: then the
+ * embedding gradient is skipped).  The alignment, length and V-gene inputs get no gradient.
+ * Weight gradients are reduced in float64; embedding gradients use float32 atomics, so
+ * their summation order (and last bits) may vary between runs.
+ *   ws / ws_bytes: at least subquad_gate_bwd_workspace_bytes(H) bytes, 256-byte aligned.
+ */
+int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                     const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                     const int32_t *align, int64_t P, const float *W1, const float *b1,
+                     const float *w2, const float *b2, int32_t H, const float *grad_fused,
+                     float *dW1, float *db1, float *dw2, float *db2, float *demb, void *ws,
+                     size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUBQUAD_H */

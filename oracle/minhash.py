@@ -96,3 +96,19 @@ def jaccard(codes_a, codes_b) -> float:
 def jaccard_estimate(sig_a: np.ndarray, sig_b: np.ndarray) -> float:
     """Fraction of hash functions on which two signatures agree."""
     return float(np.mean(sig_a == sig_b))
+
+
+def signatures_c(seqs: np.ndarray, lens: np.ndarray, M: int, seed: int) -> np.ndarray:
+    """Same as :func:`signatures`, computed by the plain C loop in ``minhash_ref.c``."""
+    from .sw import _lib
+    T = np.ascontiguousarray(hash_tables(seed, M))
+    seqs = np.ascontiguousarray(seqs, dtype=np.uint8)
+    lens = np.ascontiguousarray(lens, dtype=np.int32)
+    if lens.size and (lens.min() < 3 or lens.max() > seqs.shape[1]):
+        raise ValueError("lengths must lie in [3, stride]")
+    if seqs.size and (seqs[np.arange(seqs.shape[1])[None, :] < lens[:, None]] >= 20).any():
+        raise ValueError("residue codes must be below 20")
+    out = np.zeros((seqs.shape[0], M), dtype=np.uint64)
+    _lib().oracle_minhash3(seqs.ctypes.data, lens.ctypes.data, seqs.shape[0], seqs.shape[1],
+                           T.ctypes.data, M, out.ctypes.data)
+    return out

@@ -19,15 +19,16 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "sw_ref.c")
-_LIB = os.path.join(_HERE, "_sw_ref.so")
+_SRCS = [os.path.join(_HERE, "sw_ref.c"), os.path.join(_HERE, "minhash_ref.c")]
+_LIB = os.path.join(_HERE, "_oracle_ref.so")
 
 
 def build(force: bool = False) -> str:
-    """Compile ``sw_ref.c`` with gcc into ``oracle/_sw_ref.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile the oracle's C sources with gcc into ``oracle/_oracle_ref.so``."""
+    newest = max(os.path.getmtime(s) for s in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,6 +39,9 @@ def _lib():
     lib.oracle_sw_score.restype = ctypes.c_int
     lib.oracle_sw_score.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.oracle_minhash3.restype = None
+    lib.oracle_minhash3.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
     lib.oracle_sw_pairs.restype = None
     lib.oracle_sw_pairs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,

@@ -1,0 +1,220 @@
+"""Python binding of libsubquad: torch tensors in, torch tensors out.
+
+Argument marshalling only -- every step runs in the HIP kernels of libsubquad.so; PyTorch
+provides device memory and the current stream. Signatures are returned as int64 tensors
+holding the uint64 bit patterns.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import ERR_CAPACITY, SubquadError, check, lib
+
+HASH_SEED = 260217330
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on a GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def to_device(x, device="cuda") -> torch.Tensor:
+    """numpy / tensor -> contiguous device tensor (uint8/int32/int64/float32 preserved)."""
+    if isinstance(x, np.ndarray):
+        if x.dtype == np.uint64:
+            x = x.view(np.int64)
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device).contiguous()
+
+
+def check_seqs(seqs: torch.Tensor, lens: torch.Tensor, k: int = 3) -> int:
+    """Number of invalid rows; raises SubquadError for bad lengths or residues."""
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    bad = ctypes.c_int64(0)
+    check(lib().subquad_check_seqs(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], k,
+                                   ctypes.byref(bad), _stream()))
+    return bad.value
+
+
+def minhash(seqs: torch.Tensor, lens: torch.Tensor, M: int, seed: int = HASH_SEED, k: int = 3,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    n = seqs.shape[0]
+    if out is None:
+        out = torch.empty((n, M), dtype=torch.int64, device=seqs.device)
+    check(lib().subquad_minhash(_ptr(seqs), _ptr(lens), n, seqs.shape[1], k, M, seed & (2**64 - 1),
+                                _ptr(out), _stream()))
+    return out
+
+
+def lsh_workspace_bytes(n: int, b: int, cap: int) -> int:
+    return int(lib().subquad_lsh_workspace_bytes(n, b, cap))
+
+
+def lsh_candidates(sig: torch.Tensor, b: int, r: int, rep_offsets: torch.Tensor | None = None,
+                   cap: int | None = None, with_rows: bool = True):
+    """Candidate pairs int32 [P, 2] sorted by (i, j), and CSR row offsets int64 [n + 1]."""
+    sig = _dev(sig, torch.int64, "sig")
+    n, M = sig.shape
+    R = 1
+    offs = None
+    if rep_offsets is not None:
+        offs = _dev(rep_offsets, torch.int64, "rep_offsets")
+        R = offs.shape[0] - 1
+    cap = int(cap if cap is not None else max(1024, 8 * n))
+    dev = sig.device
+    rows = torch.empty(n + 1, dtype=torch.int64, device=dev) if with_rows else None
+    for _ in range(2):
+        ws_bytes = lsh_workspace_bytes(n, b, cap)
+        ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+        pairs = torch.empty((max(cap, 1), 2), dtype=torch.int32, device=dev)
+        P = ctypes.c_int64(0)
+        st = lib().subquad_lsh_candidates(_ptr(sig), n, M, b, r, _ptr(offs), R, _ptr(ws), ws_bytes,
+                                          _ptr(pairs), _ptr(rows), cap, ctypes.byref(P), _stream())
+        if st == ERR_CAPACITY:
+            cap = int(P.value)
+            continue
+        check(st)
+        return pairs[: P.value], rows
+    raise SubquadError(ERR_CAPACITY, "capacity retry failed")
+
+
+def self_scores(seqs: torch.Tensor, lens: torch.Tensor, subst: torch.Tensor) -> torch.Tensor:
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    subst = _dev(subst, torch.int8, "subst")
+    out = torch.empty(seqs.shape[0], dtype=torch.int32, device=seqs.device)
+    check(lib().subquad_self_scores(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], _ptr(subst),
+                                    _ptr(out), _stream()))
+    return out
+
+
+def check_subst(subst) -> None:
+    """The alignment kernels need a symmetric 20x20 matrix (host-side check)."""
+    S = subst.detach().cpu().numpy() if isinstance(subst, torch.Tensor) else np.asarray(subst)
+    if S.shape != (20, 20) or not (S == S.T).all():
+        raise ValueError("the substitution matrix must be a symmetric 20x20 matrix")
+
+
+def align_workspace_bytes(P: int) -> int:
+    return int(lib().subquad_align_workspace_bytes(P))
+
+
+def align(seqs: torch.Tensor, lens: torch.Tensor, pairs: torch.Tensor, subst: torch.Tensor,
+          gap_open: int = 10, gap_extend: int = 1, out: torch.Tensor | None = None,
+          ws: torch.Tensor | None = None) -> torch.Tensor:
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    subst = _dev(subst, torch.int8, "subst")
+    P = pairs.shape[0]
+    if out is None:
+        out = torch.empty(P, dtype=torch.int32, device=seqs.device)
+    if P == 0:
+        return out
+    need = align_workspace_bytes(P)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=seqs.device)
+    check(lib().subquad_align_batch_ws(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1],
+                                       _ptr(pairs), P, _ptr(subst), gap_open, gap_extend, _ptr(out),
+                                       _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def align_nows(seqs, lens, pairs, subst, gap_open=10, gap_extend=1) -> torch.Tensor:
+    """The entry point without a workspace (no length sort)."""
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    subst = _dev(subst, torch.int8, "subst")
+    out = torch.empty(pairs.shape[0], dtype=torch.int32, device=seqs.device)
+    check(lib().subquad_align_batch(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], _ptr(pairs),
+                                    pairs.shape[0], _ptr(subst), gap_open, gap_extend, _ptr(out),
+                                    _stream()))
+    return out
+
+
+def _gate_args(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2):
+    emb = _dev(emb, torch.float32, "emb")
+    lens = _dev(lens, torch.int32, "lens")
+    vgene = _dev(vgene, torch.int32, "vgene")
+    self_s = _dev(self_s, torch.int32, "self")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    align_s = _dev(align_s, torch.int32, "align")
+    W1 = _dev(W1, torch.float32, "W1")
+    b1 = _dev(b1, torch.float32, "b1")
+    w2 = _dev(w2, torch.float32, "w2")
+    b2 = _dev(b2, torch.float32, "b2")
+    return emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2
+
+
+def gate_fwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, return_gate: bool = False,
+             out: torch.Tensor | None = None):
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = _gate_args(
+        emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
+    P = pairs.shape[0]
+    fused = out if out is not None else torch.empty(P, dtype=torch.float32, device=emb.device)
+    gate = torch.empty(P, dtype=torch.float32, device=emb.device) if return_gate else None
+    check(lib().subquad_gate_fwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene),
+                                 _ptr(self_s), _ptr(pairs), _ptr(align_s), P, _ptr(W1), _ptr(b1),
+                                 _ptr(w2), _ptr(b2), W1.shape[0], _ptr(fused), _ptr(gate), _stream()))
+    return (fused, gate) if return_gate else fused
+
+
+def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fused,
+             need_emb: bool = True, grads=None, ws: torch.Tensor | None = None):
+    """Returns (dW1, db1, dw2, db2, demb); accumulates into ``grads`` when given."""
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = _gate_args(
+        emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
+    gf = _dev(grad_fused, torch.float32, "grad_fused")
+    H = W1.shape[0]
+    if grads is None:
+        grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(w2), torch.zeros_like(b2),
+                 torch.zeros_like(emb) if need_emb else None)
+    dW1, db1, dw2, db2, demb = grads
+    need = int(lib().subquad_gate_bwd_workspace_bytes(H))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
+    check(lib().subquad_gate_bwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene),
+                                 _ptr(self_s), _ptr(pairs), _ptr(align_s), pairs.shape[0], _ptr(W1),
+                                 _ptr(b1), _ptr(w2), _ptr(b2), H, _ptr(gf), _ptr(dW1), _ptr(db1),
+                                 _ptr(dw2), _ptr(db2), _ptr(demb), _ptr(ws), ws.numel(), _stream()))
+    return dW1, db1, dw2, db2, demb
+
+
+class GateFn(torch.autograd.Function):
+    """Fused affinity with a hand-written backward: gradients reach the embeddings and the
+    gate weights; nothing per pair is saved (the backward recomputes it)."""
+
+    @staticmethod
+    def forward(ctx, emb, W1, b1, w2, b2, pairs, align_s, self_s, lens, vgene):
+        fused = gate_fwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
+        ctx.save_for_backward(emb, W1, b1, w2, b2, pairs, align_s, self_s, lens, vgene)
+        return fused
+
+    @staticmethod
+    def backward(ctx, grad_fused):
+        emb, W1, b1, w2, b2, pairs, align_s, self_s, lens, vgene = ctx.saved_tensors
+        dW1, db1, dw2, db2, demb = gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2,
+                                            grad_fused.contiguous(), need_emb=ctx.needs_input_grad[0])
+        return demb, dW1, db1, dw2, db2, None, None, None, None, None

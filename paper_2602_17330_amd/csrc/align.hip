@@ -1,0 +1,335 @@
+// Local alignment channel on candidate pairs: Smith-Waterman score with Gotoh affine gaps
+// (the alignment affinity of Algorithm 1's affinity computation; the paper's own kernel,
+// Appendix F.3, is a global edit distance, here replaced by the local alignment score).
+//
+//   H = max(0, H_diag + S(a_x, b_y), E, F)
+//   E = max(E_left - ge, H_left - go),  F = max(F_up - ge, H_up - go),  score = max H.
+//
+// Formulation used on the GPU: E' = max(E, 0) and F' = max(F, 0) obey
+//   E' = max(E'_left - ge, H_left - go, 0),  F' = max(F'_up - ge, H_up - go, 0),
+//   H = max(H_diag + S, E', F'),
+// which is the recurrence above with the 0 of H folded into the gap states (by induction:
+// a negative E can only lower a maximum that already contains 0).  Every cell is then
+// two v_max3, one add and three subtractions, with no minus-infinity sentinel.
+//
+// Mapping to CDNA4: one lane per pair (inter-pair parallelism; CDR3s are short, so a pair
+// fits in registers).  The shorter sequence runs down the unrolled, register-resident
+// rows (ROWS = its length rounded up to 8), the longer one across the column loop.
+// Pairs are first counting-sorted by (rows bucket, longer length), so the lanes of a wave
+// have the same unroll and nearly the same trip count.  Substitution scores come from an
+// LDS table that packs S(a_x, c) and S(a_x+1, c) for a row pair and a column residue c
+// into one 32-bit word (one ds_read per two cells).
+#include "common.h"
+#include "radix.h"
+
+namespace subquad {
+
+constexpr int kAlignThreads = 256;
+constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..64)
+constexpr int kMaskCode = 20;          // rows past the shorter sequence's end
+constexpr int kMaskScore = -4096;
+constexpr int kCodes = 21;
+constexpr int kS2Words = 20 * kCodes * kCodes;
+
+__device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+__device__ __forceinline__ void pair_lengths(const int32_t *__restrict__ pairs, const int32_t *__restrict__ lens,
+                                             int64_t p, int &lmin, int &lmax) {
+    int la = lens[pairs[2 * p]], lb = lens[pairs[2 * p + 1]];
+    lmin = min(max(la, 0), 64);
+    lmax = min(max(lb, 0), 64);
+    if (lmin > lmax) { int t = lmin; lmin = lmax; lmax = t; }
+}
+
+__device__ __forceinline__ bool pair_ok(const int32_t *__restrict__ pairs, int64_t n, int64_t p) {
+    int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+    return i >= 0 && j >= 0 && i < n && j < n;
+}
+
+__device__ __forceinline__ int align_key(int lmin, int lmax) {
+    int rb = (max(lmin, 1) + 7) >> 3;  // 1..8
+    return (rb - 1) * 64 + (max(lmax, 1) - 1);
+}
+
+__global__ __launch_bounds__(256) void align_hist_kernel(const int32_t *__restrict__ pairs,
+                                                         const int32_t *__restrict__ lens, int64_t n, int64_t P,
+                                                         uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kAlignKeyBins];
+    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        int lmin = 1, lmax = 1;
+        if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
+        atomicAdd(&h[align_key(lmin, lmax)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x)
+        if (h[k]) atomicAdd(&hist[k], h[k]);
+}
+
+__global__ void align_zero_kernel(uint32_t *__restrict__ hist) {
+    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x) hist[k] = 0;
+}
+
+// Single block of 512 threads: exclusive scan of the 512 bins (in place).
+__global__ __launch_bounds__(kAlignKeyBins) void align_scan_kernel(uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s[kAlignKeyBins];
+    const int t = threadIdx.x;
+    uint32_t v = hist[t];
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kAlignKeyBins; off <<= 1) {
+        uint32_t o = t >= off ? s[t - off] : 0;
+        __syncthreads();
+        s[t] += o;
+        __syncthreads();
+    }
+    hist[t] = s[t] - v;
+}
+
+__global__ __launch_bounds__(256) void align_scatter_kernel(const int32_t *__restrict__ pairs,
+                                                            const int32_t *__restrict__ lens, int64_t n, int64_t P,
+                                                            uint32_t *__restrict__ cursor,
+                                                            uint32_t *__restrict__ perm) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        int lmin = 1, lmax = 1;
+        if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
+        uint32_t pos = atomicAdd(&cursor[align_key(lmin, lmax)], 1u);
+        if ((int64_t)pos < P) perm[pos] = (uint32_t)p;
+    }
+}
+
+// DP of one pair in one lane.  a: the shorter sequence (rows), b: the longer (columns).
+template <int ROWS>
+__device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la, const uint8_t *__restrict__ brow,
+                                       int lb, const uint32_t *__restrict__ S2, int go, int ge) {
+    // byte offsets into S2 of the row pair (x, x+1), without the column-residue part
+    uint32_t idx2[ROWS / 2];
+#pragma unroll
+    for (int k = 0; k < ROWS / 2; ++k) {
+        int x0 = 2 * k, x1 = 2 * k + 1;
+        int c0 = x0 < la ? min((int)arow[x0], 19) : kMaskCode;
+        int c1 = x1 < la ? min((int)arow[x1], 19) : kMaskCode;
+        idx2[k] = (uint32_t)(c0 * kCodes + c1);
+    }
+    int Hp[ROWS], E[ROWS], HG[ROWS];
+#pragma unroll
+    for (int x = 0; x < ROWS; ++x) {
+        Hp[x] = 0;
+        E[x] = 0;
+        HG[x] = -go;
+    }
+    int best = 0;
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow);
+    uint32_t word = bw[0];
+    for (int y0 = 0; y0 < lb; y0 += 4) {
+        uint32_t cur = word;
+        if (y0 + 4 < lb) word = bw[(y0 >> 2) + 1];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            if (y0 + k4 < lb) {
+                int c = min((int)((cur >> (8 * k4)) & 0xFFu), 19);
+                const uint32_t *col = S2 + c * (kCodes * kCodes);
+                int diag = 0, f = 0, hup_go = -go;
+#pragma unroll
+                for (int k = 0; k < ROWS / 2; ++k) {
+                    uint32_t w = col[idx2[k]];
+                    int s0 = (int)(int16_t)(w & 0xFFFFu);
+                    int s1 = (int)w >> 16;
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int x = 2 * k + h2;
+                        const int s = h2 ? s1 : s0;
+                        int e = max3i(E[x] - ge, HG[x], 0);
+                        f = max3i(f - ge, hup_go, 0);
+                        int h = max3i(diag + s, e, f);
+                        diag = Hp[x];
+                        Hp[x] = h;
+                        E[x] = e;
+                        HG[x] = h - go;
+                        hup_go = HG[x];
+                        best = max(best, h);
+                    }
+                }
+            }
+        }
+    }
+    return best;
+}
+
+template <int MAXROWS>
+__global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__restrict__ seqs,
+                                                              const int32_t *__restrict__ lens, int64_t n,
+                                                              int32_t stride,
+                                                              const int32_t *__restrict__ pairs, int64_t P,
+                                                              const uint32_t *__restrict__ perm,
+                                                              const int8_t *__restrict__ subst, int go, int ge,
+                                                              int32_t *__restrict__ scores) {
+    __shared__ uint32_t S2[kS2Words];
+    for (int e = threadIdx.x; e < kS2Words; e += blockDim.x) {
+        int c = e / (kCodes * kCodes);
+        int rem = e - c * (kCodes * kCodes);
+        int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
+        int s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : kMaskScore;
+        int s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : kMaskScore;
+        S2[e] = ((uint32_t)(uint16_t)(int16_t)s0) | ((uint32_t)(uint16_t)(int16_t)s1 << 16);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves_total = ceil_div(P, 64);
+    const int64_t wave0 = (int64_t)blockIdx.x * (kAlignThreads / 64) + (threadIdx.x >> 6);
+    const int64_t wstep = (int64_t)gridDim.x * (kAlignThreads / 64);
+    for (int64_t wv = wave0; wv < nwaves_total; wv += wstep) {
+        const int64_t idx = wv * 64 + lane;
+        bool valid = idx < P;
+        int64_t p = 0;
+        int la = 0, lb = 0;
+        const uint8_t *arow = seqs, *brow = seqs;
+        bool bad = false;
+        if (valid) {
+            p = perm ? (int64_t)perm[idx] : idx;
+            valid = p < P;
+        }
+        if (valid && !pair_ok(pairs, n, p)) {
+            bad = true;
+            valid = false;
+            scores[p] = -1;
+        }
+        (void)bad;
+        if (valid) {
+            int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+            int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
+            if (li <= lj) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
+            else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
+        }
+        // the wave's unroll: the largest rows bucket among its lanes (sorted input keeps it tight)
+        int rb = valid ? (max(la, 1) + 7) >> 3 : 1;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) rb = max(rb, __shfl_xor(rb, off, 64));
+        rb = __builtin_amdgcn_readfirstlane(rb);
+        int best = 0;
+        if (valid) {
+            la = min(la, MAXROWS);
+            switch (rb) {
+                case 1: best = sw_lane<8>(arow, la, brow, lb, S2, go, ge); break;
+                case 2: best = sw_lane<16>(arow, la, brow, lb, S2, go, ge); break;
+                case 3: best = sw_lane<24>(arow, la, brow, lb, S2, go, ge); break;
+                case 4: best = sw_lane<32>(arow, la, brow, lb, S2, go, ge); break;
+                default:
+                    if constexpr (MAXROWS > 32) {
+                        if (rb <= 6) best = sw_lane<48>(arow, la, brow, lb, S2, go, ge);
+                        else best = sw_lane<64>(arow, la, brow, lb, S2, go, ge);
+                    }
+                    break;
+            }
+            scores[p] = best;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void self_scores_kernel(const uint8_t *__restrict__ seqs,
+                                                          const int32_t *__restrict__ lens, int64_t n,
+                                                          int32_t stride, const int8_t *__restrict__ subst,
+                                                          int32_t *__restrict__ self) {
+    __shared__ int diag[20];
+    if (threadIdx.x < 20) diag[threadIdx.x] = subst[threadIdx.x * 21];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t *row = seqs + i * stride;
+        int L = min(lens[i], stride), s = 0;
+        for (int x = 0; x < L; ++x) s += diag[min((int)row[x], 19)];
+        self[i] = s;
+    }
+}
+
+struct AlignScratch {
+    uint32_t *hist;
+    uint32_t *perm;
+};
+
+}  // namespace subquad
+
+using namespace subquad;
+
+extern "C" int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                   const int8_t *subst, int32_t *self, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0, SUBQUAD_ERR_ARG, "n must be >= 0");
+    SQ_REQUIRE(n == 0 || (seqs && lens && subst && self), SUBQUAD_ERR_ARG, "null pointer argument");
+    SQ_REQUIRE(stride >= 1 && stride <= 4096, SUBQUAD_ERR_ARG, "stride out of range");
+    if (n == 0) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)device_cus() * 16);
+    self_scores_kernel<<<(unsigned)blocks, 256, 0, st>>>(seqs, lens, n, stride, subst, self);
+    SQ_LAUNCHED("self_scores_kernel");
+    return SUBQUAD_OK;
+}
+
+// The length sort needs P + 512 words of scratch; it is taken from a stream-ordered
+// allocation only when the caller passes no workspace (the plain entry point below).
+static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, const int32_t *pairs, int64_t P,
+                     const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st) {
+    uint32_t *hist = scratch;
+    uint32_t *perm = scratch + kAlignKeyBins;
+    const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
+    align_zero_kernel<<<1, 512, 0, st>>>(hist);
+    SQ_LAUNCHED("align_zero_kernel");
+    align_hist_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, hist);
+    SQ_LAUNCHED("align_hist_kernel");
+    align_scan_kernel<<<1, kAlignKeyBins, 0, st>>>(hist);
+    SQ_LAUNCHED("align_scan_kernel");
+    align_scatter_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, hist, perm);
+    SQ_LAUNCHED("align_scatter_kernel");
+    const int64_t waves = ceil_div(P, 64);
+    const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64), (int64_t)device_cus() * 8);
+    if (stride <= 32)
+        align_kernel<32><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, subst, go,
+                                                                       ge, scores);
+    else
+        align_kernel<64><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, subst, go,
+                                                                       ge, scores);
+    SQ_LAUNCHED("align_kernel");
+    return SUBQUAD_OK;
+}
+
+extern "C" size_t subquad_align_workspace_bytes(int64_t P) {
+    if (P < 0) return 0;
+    return align_up(sizeof(uint32_t) * (size_t)(P + kAlignKeyBins), 256);
+}
+
+extern "C" int subquad_align_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                      const int32_t *pairs, int64_t P, const int8_t *subst, int32_t gap_open,
+                                      int32_t gap_extend, int32_t *scores, void *ws, size_t ws_bytes,
+                                      void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0 && P >= 0, SUBQUAD_ERR_ARG, "n and P must be >= 0");
+    SQ_REQUIRE(P == 0 || (seqs && lens && pairs && subst && scores), SUBQUAD_ERR_ARG, "null pointer argument");
+    SQ_REQUIRE(stride >= 4 && stride <= 64 && stride % 4 == 0, SUBQUAD_ERR_ARG,
+               "stride must be a multiple of 4 in 4..64 (got %d)", stride);
+    SQ_REQUIRE(gap_extend >= 0 && gap_open >= gap_extend && gap_open <= 1000, SUBQUAD_ERR_ARG,
+               "need 0 <= gap_extend <= gap_open <= 1000");
+    SQ_REQUIRE(P < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "P must be below 2^32");
+    if (P == 0) return SUBQUAD_OK;
+    SQ_REQUIRE(ws && ws_bytes >= subquad_align_workspace_bytes(P), SUBQUAD_ERR_WORKSPACE,
+               "alignment workspace too small");
+    return align_run(seqs, lens, n, stride, pairs, P, subst, gap_open, gap_extend, scores, static_cast<uint32_t *>(ws),
+                     as_stream(stream));
+}
+
+extern "C" int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                   const int32_t *pairs, int64_t P, const int8_t *subst, int32_t gap_open,
+                                   int32_t gap_extend, int32_t *scores, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0 && P >= 0, SUBQUAD_ERR_ARG, "n and P must be >= 0");
+    if (P == 0) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    size_t bytes = subquad_align_workspace_bytes(P);
+    void *ws = nullptr;
+    SQ_HIP(hipMallocAsync(&ws, bytes, st));
+    int rc = subquad_align_batch_ws(seqs, lens, n, stride, pairs, P, subst, gap_open, gap_extend, scores, ws, bytes,
+                                    stream);
+    hipError_t fe = hipFreeAsync(ws, st);
+    if (rc != SUBQUAD_OK) return rc;
+    SQ_HIP(fe);
+    return SUBQUAD_OK;
+}

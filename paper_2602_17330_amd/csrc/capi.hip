@@ -1,0 +1,97 @@
+// Library-wide entry points: error reporting, version, sequence validation.
+#include <cstdarg>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace subquad {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int device_cus() {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+// One thread per row: bit 0 = bad length, bit 1 = bad residue; counts go to out[0], out[1].
+__global__ void check_seqs_kernel(const uint8_t *__restrict__ seqs, const int32_t *__restrict__ lens,
+                                  int64_t n, int32_t stride, int32_t k,
+                                  unsigned long long *__restrict__ out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t L = lens[i];
+    if (L < k || L > stride) {
+        atomicAdd(&out[0], 1ull);
+        return;
+    }
+    const uint8_t *row = seqs + i * (int64_t)stride;
+    for (int32_t p = 0; p < L; ++p) {
+        if (row[p] >= 20) {
+            atomicAdd(&out[1], 1ull);
+            return;
+        }
+    }
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace subquad
+
+using namespace subquad;
+
+extern "C" const char *subquad_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *subquad_version(void) { return "subquad 0.1 (gfx950)"; }
+
+extern "C" int subquad_check_seqs(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                  int32_t k, int64_t *n_bad, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0, SUBQUAD_ERR_ARG, "n must be >= 0");
+    SQ_REQUIRE(n == 0 || (seqs && lens), SUBQUAD_ERR_ARG, "null sequence or length pointer");
+    SQ_REQUIRE(stride >= 1 && stride <= 4096, SUBQUAD_ERR_ARG, "stride out of range");
+    SQ_REQUIRE(k >= 1 && k <= 5, SUBQUAD_ERR_ARG, "k must be in 1..5");
+    if (n_bad) *n_bad = 0;
+    if (n == 0) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    unsigned long long *dcount = nullptr;
+    SQ_HIP(hipMallocAsync((void **)&dcount, 2 * sizeof(unsigned long long), st));
+    fill_u64_kernel<<<1, 64, 0, st>>>(dcount, 2, 0ull);
+    check_seqs_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(seqs, lens, n, stride, k, dcount);
+    unsigned long long host[2] = {0, 0};
+    hipError_t e1 = hipMemcpyAsync(host, dcount, sizeof(host), hipMemcpyDeviceToHost, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    hipError_t e3 = hipFreeAsync(dcount, st);
+    SQ_HIP(e1);
+    SQ_HIP(e2);
+    SQ_HIP(e3);
+    if (n_bad) *n_bad = (int64_t)(host[0] + host[1]);
+    SQ_REQUIRE(host[0] == 0, SUBQUAD_ERR_LENGTH, "%llu sequence(s) with length outside [k, stride]", host[0]);
+    SQ_REQUIRE(host[1] == 0, SUBQUAD_ERR_RESIDUE, "%llu sequence(s) with a residue code >= 20", host[1]);
+    return SUBQUAD_OK;
+}

@@ -1,0 +1,65 @@
+// Shared host/device helpers of libsubquad: status handling, launch checks, wave helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "subquad.h"
+
+namespace subquad {
+
+// Thread-local message for subquad_last_error().
+void set_error(const char *fmt, ...);
+void clear_error();
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define SQ_REQUIRE(cond, code, ...)             \
+    do {                                        \
+        if (!(cond)) {                          \
+            ::subquad::set_error(__VA_ARGS__);  \
+            return (code);                      \
+        }                                       \
+    } while (0)
+
+#define SQ_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t err__ = (expr);                                                       \
+        if (err__ != hipSuccess) {                                                       \
+            ::subquad::set_error("%s failed: %s", #expr, hipGetErrorString(err__));      \
+            return SUBQUAD_ERR_HIP;                                                      \
+        }                                                                                \
+    } while (0)
+
+// Checks the launch that was just enqueued.
+#define SQ_LAUNCHED(name)                                                                \
+    do {                                                                                 \
+        hipError_t err__ = hipGetLastError();                                            \
+        if (err__ != hipSuccess) {                                                       \
+            ::subquad::set_error("launch of %s failed: %s", name, hipGetErrorString(err__)); \
+            return SUBQUAD_ERR_HIP;                                                      \
+        }                                                                                \
+    } while (0)
+
+constexpr int kWave = 64;
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Number of compute units of the current device (cached per process per device).
+int device_cus();
+
+// Upper bound of a repertoire id: the r with rep_offsets[r] <= i < rep_offsets[r+1].
+__device__ __forceinline__ int64_t rep_of(const int64_t *__restrict__ offs, int64_t R, int64_t i) {
+    int64_t lo = 0, hi = R;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (offs[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace subquad

@@ -1,0 +1,411 @@
+// Per-pair dynamic affinity fusion (Sec. 3.6, Eq. (wm) and (afused); sigmoid channel weight
+// as in Eq. (alpha)), forward and backward.
+//
+//   s = A / sqrt(S_i S_j), c = cos(e_i, e_j), x = (s, c, |L_i - L_j|, [V_i == V_j])
+//   z = W1 x + b1, h = relu(z), u = w2 . h + b2, g = sigmoid(u)   (softmax over (u, 0))
+//   f = g s + (1 - g) c
+// Backward of L = sum_p gf_p f_p, recomputing every intermediate:
+//   u_bar = gf (s - c) g (1 - g);  dw2 += u_bar h;  db2 += u_bar
+//   z_bar = u_bar w2 [z > 0];      dW1 += z_bar x^T; db1 += z_bar
+//   c_bar = gf (1 - g) + (W1^T z_bar)_c
+//   de_i += c_bar (e_j / (|e_i||e_j|) - c e_i / |e_i|^2), and symmetrically for e_j.
+//
+// Mapping to CDNA4: a group of 16 lanes per pair; lane l of the group loads float4 slices
+// l, l + 16, ... of both embeddings (256-byte coalesced segments) and owns hidden units
+// l, l + 16, ...; dot products and the logit are reduced with 16-wide shuffles.  A group
+// walks a contiguous chunk of the (row-sorted) pair list, so e_i, |e_i| and, in the
+// backward, the gradient of e_i stay in registers while the first index repeats.  Weight
+// gradients accumulate per lane in float64 and are reduced per block, then once per block
+// into a float64 workspace.
+#include "common.h"
+
+namespace subquad {
+
+constexpr int kGateThreads = 256;
+constexpr int kGroup = 16;
+
+struct GateIn {
+    const float *emb;
+    int64_t n;
+    int32_t d;
+    const int32_t *lens, *vgene, *self, *pairs, *align;
+    int64_t P;
+    const float *W1, *b1, *w2, *b2;
+    int32_t H;
+};
+
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int off = kGroup / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kGroup);
+    return v;
+}
+
+template <int NV>
+__device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t row, int d4, int l, float4 (&v)[NV]) {
+    const float4 *r = reinterpret_cast<const float4 *>(emb) + row * d4;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        int c = l + kGroup * k;
+        v[k] = c < d4 ? r[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+
+// Forward quantities of one pair (all lanes of the group hold the same values on return,
+// except z/h which are the lane's own hidden units).
+template <int NV, int UNITS>
+struct PairState {
+    float s, c, x2, x3, ni, nj, g, u;
+    bool ok;
+    float z[UNITS];
+};
+
+template <int NV, int UNITS>
+__device__ __forceinline__ void pair_forward(const GateIn &in, int64_t p, const float4 (&ei)[NV], float ni2,
+                                             const float4 (&ej)[NV], int64_t i, int64_t j,
+                                             const float (&W1)[UNITS][4], const float (&b1)[UNITS],
+                                             const float (&w2)[UNITS], float b2, PairState<NV, UNITS> &st) {
+    float dot = 0.f, nj2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        dot += dot4(ei[k], ej[k]);
+        nj2 += dot4(ej[k], ej[k]);
+    }
+    dot = group_sum(dot);
+    nj2 = group_sum(nj2);
+    st.ni = sqrtf(ni2);
+    st.nj = sqrtf(nj2);
+    const float den = st.ni * st.nj;
+    st.ok = den >= 1e-12f;
+    st.c = st.ok ? dot / den : 0.f;
+    const float si = (float)in.self[i], sj = (float)in.self[j];
+    st.s = (float)in.align[p] / sqrtf(si * sj);
+    st.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
+    st.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
+    float part = 0.f;
+#pragma unroll
+    for (int k = 0; k < UNITS; ++k) {
+        float z = W1[k][0] * st.s + W1[k][1] * st.c + W1[k][2] * st.x2 + W1[k][3] * st.x3 + b1[k];
+        st.z[k] = z;
+        part += w2[k] * fmaxf(z, 0.f);
+    }
+    st.u = group_sum(part) + b2;
+    st.g = 1.f / (1.f + expf(-st.u));
+}
+
+template <int UNITS>
+__device__ __forceinline__ void load_weights(const GateIn &in, int l, float (&W1)[UNITS][4], float (&b1)[UNITS],
+                                             float (&w2)[UNITS], float &b2) {
+#pragma unroll
+    for (int k = 0; k < UNITS; ++k) {
+        int unit = l + kGroup * k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W1[k][q] = in.W1[unit * 4 + q];
+        b1[k] = in.b1[unit];
+        w2[k] = in.w2[unit];
+    }
+    b2 = in.b2[0];
+}
+
+template <int NV, int UNITS>
+__global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float *__restrict__ fused,
+                                                                float *__restrict__ gate) {
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = ceil_div(in.P, ngroups);
+    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    if (p0 >= p1) return;
+    const int d4 = in.d >> 2;
+    float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
+    load_weights<UNITS>(in, l, W1, b1, w2, b2);
+    float4 ei[NV], ej[NV];
+    float ni2 = 0.f;
+    int64_t cur_i = -1;
+    for (int64_t p = p0; p < p1; ++p) {
+        const int64_t i = in.pairs[2 * p], j = in.pairs[2 * p + 1];
+        if (i < 0 || j < 0 || i >= in.n || j >= in.n) {  // out-of-range pair: no access
+            if (l == 0) {
+                fused[p] = __builtin_nanf("");
+                if (gate) gate[p] = __builtin_nanf("");
+            }
+            continue;
+        }
+        if (i != cur_i) {
+            load_row<NV>(in.emb, i, d4, l, ei);
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
+            ni2 = group_sum(a);
+            cur_i = i;
+        }
+        load_row<NV>(in.emb, j, d4, l, ej);
+        PairState<NV, UNITS> st;
+        pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
+        if (l == 0) {
+            fused[p] = st.c + st.g * (st.s - st.c);
+            if (gate) gate[p] = st.g;
+        }
+    }
+}
+
+// Workspace layout (doubles): dW1[H][4], db1[H], dw2[H], db2.
+template <int NV, int UNITS>
+__global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
+                                                                float *__restrict__ demb, double *__restrict__ wacc) {
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = ceil_div(in.P, ngroups);
+    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    const int d4 = in.d >> 2;
+    float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
+    load_weights<UNITS>(in, l, W1, b1, w2, b2);
+    double aW1[UNITS][4], ab1[UNITS], aw2[UNITS], ab2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < UNITS; ++k) {
+        ab1[k] = 0.0;
+        aw2[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) aW1[k][q] = 0.0;
+    }
+    float4 ei[NV], ej[NV], gi[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ni2 = 0.f;
+    int64_t cur_i = -1;
+    auto flush_i = [&](int64_t row) {
+        if (!demb || row < 0) return;
+        float *base = demb + row * (int64_t)in.d;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            int c = l + kGroup * k;
+            if (c < d4) {
+                atomicAdd(base + 4 * c + 0, gi[k].x);
+                atomicAdd(base + 4 * c + 1, gi[k].y);
+                atomicAdd(base + 4 * c + 2, gi[k].z);
+                atomicAdd(base + 4 * c + 3, gi[k].w);
+            }
+            gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    for (int64_t p = p0; p < p1; ++p) {
+        const int64_t i = in.pairs[2 * p], j = in.pairs[2 * p + 1];
+        if (i < 0 || j < 0 || i >= in.n || j >= in.n) continue;  // out-of-range pair: skipped
+        if (i != cur_i) {
+            flush_i(cur_i);
+            load_row<NV>(in.emb, i, d4, l, ei);
+            float a = 0.f;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
+            ni2 = group_sum(a);
+            cur_i = i;
+        }
+        load_row<NV>(in.emb, j, d4, l, ej);
+        PairState<NV, UNITS> st;
+        pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
+        const float gf = gfused[p];
+        const float ubar = gf * (st.s - st.c) * st.g * (1.f - st.g);
+        const float x[4] = {st.s, st.c, st.x2, st.x3};
+        float xc = 0.f;
+#pragma unroll
+        for (int k = 0; k < UNITS; ++k) {
+            const float h = fmaxf(st.z[k], 0.f);
+            aw2[k] += (double)(ubar * h);
+            const float zbar = st.z[k] > 0.f ? ubar * w2[k] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) aW1[k][q] += (double)(zbar * x[q]);
+            ab1[k] += (double)zbar;
+            xc += zbar * W1[k][1];
+        }
+        if (l == 0) ab2 += (double)ubar;
+        const float cbar = gf * (1.f - st.g) + group_sum(xc);
+        if (demb && st.ok) {
+            const float inv = 1.f / (st.ni * st.nj);
+            const float ci = st.c / (st.ni * st.ni), cj = st.c / (st.nj * st.nj);
+            float *bj = demb + j * (int64_t)in.d;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                int c = l + kGroup * k;
+                if (c < d4) {
+                    gi[k].x += cbar * (ej[k].x * inv - ci * ei[k].x);
+                    gi[k].y += cbar * (ej[k].y * inv - ci * ei[k].y);
+                    gi[k].z += cbar * (ej[k].z * inv - ci * ei[k].z);
+                    gi[k].w += cbar * (ej[k].w * inv - ci * ei[k].w);
+                    atomicAdd(bj + 4 * c + 0, cbar * (ei[k].x * inv - cj * ej[k].x));
+                    atomicAdd(bj + 4 * c + 1, cbar * (ei[k].y * inv - cj * ej[k].y));
+                    atomicAdd(bj + 4 * c + 2, cbar * (ei[k].z * inv - cj * ej[k].z));
+                    atomicAdd(bj + 4 * c + 3, cbar * (ei[k].w * inv - cj * ej[k].w));
+                }
+            }
+        }
+    }
+    flush_i(cur_i);
+
+    // Block reduction of the weight gradients: lanes with equal l hold the same units.
+    constexpr int kVals = 6 * UNITS;
+    double v[kVals];
+#pragma unroll
+    for (int k = 0; k < UNITS; ++k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[k * 6 + q] = aW1[k][q];
+        v[k * 6 + 4] = ab1[k];
+        v[k * 6 + 5] = aw2[k];
+    }
+#pragma unroll
+    for (int m = 0; m < kVals; ++m) {
+        v[m] += __shfl_xor(v[m], 16, 64);
+        v[m] += __shfl_xor(v[m], 32, 64);
+    }
+    ab2 += __shfl_xor(ab2, 16, 64);
+    ab2 += __shfl_xor(ab2, 32, 64);
+    __shared__ double red[kGateThreads / 64][kGroup][kVals + 1];
+    const int w = threadIdx.x >> 6, lw = threadIdx.x & 63;
+    if (lw < kGroup) {
+#pragma unroll
+        for (int m = 0; m < kVals; ++m) red[w][lw][m] = v[m];
+        red[w][lw][kVals] = ab2;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kGroup * (kVals + 1); e += kGateThreads) {
+        const int ll = e / (kVals + 1), m = e - ll * (kVals + 1);
+        double s = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < kGateThreads / 64; ++ww) s += red[ww][ll][m];
+        if (m == kVals) {
+            if (ll == 0) atomicAdd(&wacc[in.H * 6], s);
+            continue;
+        }
+        const int k = m / 6, q = m - k * 6;
+        const int unit = ll + kGroup * k;
+        double *dst;
+        if (q < 4) dst = &wacc[unit * 4 + q];
+        else if (q == 4) dst = &wacc[in.H * 4 + unit];
+        else dst = &wacc[in.H * 5 + unit];
+        atomicAdd(dst, s);
+    }
+}
+
+__global__ void gate_ws_zero_kernel(double *__restrict__ wacc, int count) {
+    for (int k = threadIdx.x; k < count; k += blockDim.x) wacc[k] = 0.0;
+}
+
+__global__ void gate_ws_finish_kernel(const double *__restrict__ wacc, int H, float *__restrict__ dW1,
+                                      float *__restrict__ db1, float *__restrict__ dw2, float *__restrict__ db2) {
+    for (int k = threadIdx.x; k < H * 6 + 1; k += blockDim.x) {
+        float v = (float)wacc[k];
+        if (k < H * 4) dW1[k] += v;
+        else if (k < H * 5) db1[k - H * 4] += v;
+        else if (k < H * 6) dw2[k - H * 5] += v;
+        else db2[0] += v;
+    }
+}
+
+static int gate_validate(const GateIn &in) {
+    SQ_REQUIRE(in.n >= 0 && in.P >= 0, SUBQUAD_ERR_ARG, "n and P must be >= 0");
+    SQ_REQUIRE(in.d >= 4 && in.d <= 1024 && in.d % 4 == 0, SUBQUAD_ERR_ARG, "d must be a multiple of 4 in 4..1024");
+    SQ_REQUIRE(in.H >= 16 && in.H <= 256 && in.H % 16 == 0, SUBQUAD_ERR_ARG, "H must be a multiple of 16 in 16..256");
+    SQ_REQUIRE(in.P == 0 || (in.emb && in.lens && in.vgene && in.self && in.pairs && in.align), SUBQUAD_ERR_ARG,
+               "null input pointer");
+    SQ_REQUIRE(in.W1 && in.b1 && in.w2 && in.b2, SUBQUAD_ERR_ARG, "null weight pointer");
+    SQ_REQUIRE(((uintptr_t)in.emb & 15) == 0, SUBQUAD_ERR_ARG, "emb must be 16-byte aligned");
+    return SUBQUAD_OK;
+}
+
+static int64_t gate_blocks(int64_t P) {
+    // enough groups to fill the chip, each with a contiguous chunk of pairs
+    int64_t groups = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * 64));
+    return ceil_div(groups, kGateThreads / kGroup);
+}
+
+template <int NV>
+static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t st) {
+    const int64_t blocks = gate_blocks(in.P);
+    switch (in.H / kGroup) {
+#define SQ_CASE(U) \
+    case U: gate_fwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, fused, gate); break;
+        SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
+#undef SQ_CASE
+        default:
+            set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
+            return SUBQUAD_ERR_ARG;
+    }
+    SQ_LAUNCHED("gate_fwd_kernel");
+    return SUBQUAD_OK;
+}
+
+template <int NV>
+static int gate_bwd_nv(const GateIn &in, const float *gf, float *demb, double *wacc, hipStream_t st) {
+    const int64_t blocks = gate_blocks(in.P);
+    switch (in.H / kGroup) {
+#define SQ_CASE(U) \
+    case U: gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, demb, wacc); break;
+        SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
+#undef SQ_CASE
+        default:
+            set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
+            return SUBQUAD_ERR_ARG;
+    }
+    SQ_LAUNCHED("gate_bwd_kernel");
+    return SUBQUAD_OK;
+}
+
+}  // namespace subquad
+
+using namespace subquad;
+
+extern "C" int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens, const int32_t *vgene,
+                                const int32_t *self, const int32_t *pairs, const int32_t *align, int64_t P,
+                                const float *W1, const float *b1, const float *w2, const float *b2, int32_t H,
+                                float *fused, float *gate, void *stream) {
+    clear_error();
+    GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H};
+    int rc = gate_validate(in);
+    if (rc != SUBQUAD_OK) return rc;
+    SQ_REQUIRE(P == 0 || fused, SUBQUAD_ERR_ARG, "null output pointer");
+    if (P == 0) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    const int nv = (int)ceil_div(d / 4, kGroup);
+    if (nv <= 1) return gate_fwd_nv<1>(in, fused, gate, st);
+    if (nv <= 2) return gate_fwd_nv<2>(in, fused, gate, st);
+    if (nv <= 4) return gate_fwd_nv<4>(in, fused, gate, st);
+    if (nv <= 8) return gate_fwd_nv<8>(in, fused, gate, st);
+    return gate_fwd_nv<16>(in, fused, gate, st);
+}
+
+extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H) {
+    if (H <= 0) return 0;
+    return align_up(sizeof(double) * (size_t)(H * 6 + 1), 256);
+}
+
+extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens, const int32_t *vgene,
+                                const int32_t *self, const int32_t *pairs, const int32_t *align, int64_t P,
+                                const float *W1, const float *b1, const float *w2, const float *b2, int32_t H,
+                                const float *grad_fused, float *dW1, float *db1, float *dw2, float *db2, float *demb,
+                                void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H};
+    int rc = gate_validate(in);
+    if (rc != SUBQUAD_OK) return rc;
+    SQ_REQUIRE(dW1 && db1 && dw2 && db2, SUBQUAD_ERR_ARG, "null weight-gradient pointer");
+    SQ_REQUIRE(P == 0 || grad_fused, SUBQUAD_ERR_ARG, "null grad_fused");
+    SQ_REQUIRE(ws && ws_bytes >= subquad_gate_bwd_workspace_bytes(H), SUBQUAD_ERR_WORKSPACE,
+               "gate workspace too small");
+    SQ_REQUIRE(((uintptr_t)ws & 255) == 0, SUBQUAD_ERR_ARG, "workspace must be 256-byte aligned");
+    if (P == 0) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    double *wacc = static_cast<double *>(ws);
+    gate_ws_zero_kernel<<<1, 256, 0, st>>>(wacc, H * 6 + 1);
+    SQ_LAUNCHED("gate_ws_zero_kernel");
+    const int nv = (int)ceil_div(d / 4, kGroup);
+    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, demb, wacc, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, demb, wacc, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, demb, wacc, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, demb, wacc, st);
+    else rc = gate_bwd_nv<16>(in, grad_fused, demb, wacc, st);
+    if (rc != SUBQUAD_OK) return rc;
+    gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, H, dW1, db1, dw2, db2);
+    SQ_LAUNCHED("gate_ws_finish_kernel");
+    return SUBQUAD_OK;
+}

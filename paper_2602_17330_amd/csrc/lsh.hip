@@ -1,0 +1,298 @@
+// MinHash LSH banding into the candidate list (Algorithm 1, preprocessing: build the MinHash
+// index and generate CAND; index of Sec. 4.2; retrieval cost O(|C|) + O(n log n),
+// Appendix B).
+//
+// A pair (i, j), i < j, of one repertoire is a candidate iff for some band beta the r-tuples
+// sig[i][beta*r .. beta*r + r) and sig[j][...] are exactly equal.  Steps:
+//   1. band records: for every (beta, i) a 64-bit mix of (tuple, repertoire); the record is
+//      (top 32 bits of the mix) << 32 | (beta * n + i), written band-major.  An 8-bit
+//      fingerprint of every (i, beta) mix goes to a row-major table F[n][b].
+//   2. stable radix sort of the records on their top 32 bits.  Stability keeps records with
+//      equal mix bits in (beta, i) order, so each bucket (equal mix bits, equal band) is a
+//      contiguous run with ascending i.
+//   3. run scan: for every record, every later record of its run is a potential partner.
+//      The pair is kept only if (a) both rows are in one repertoire, (b) the band tuples are
+//      exactly equal, and (c) beta is the FIRST band in which the tuples are equal (earlier
+//      bands are tested through F first and confirmed on the tuples), so each candidate is
+//      emitted exactly once.  Kept pairs are appended as keys (i << nb) | j.
+//   4. radix sort of the pair keys gives the canonical (i, j) order; then the pair list and
+//      the CSR row offsets are written.
+// The mixing function only decides which records meet; equality is always decided on the
+// signature words themselves, so results never depend on hash collisions.
+#include "radix.h"
+
+namespace subquad {
+
+constexpr int kKeysTileSeqs = 64;
+constexpr int kKeysThreads = 256;
+constexpr int kEmitThreads = 256;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 33)) * 0xFF51AFD7ED558CCDull;
+    z = (z ^ (z >> 33)) * 0xC4CEB9FE1A85EC53ull;
+    return z ^ (z >> 33);
+}
+
+// Step 1. Block = 64 sequences x b bands.  Reads of the signature rows are contiguous
+// (item e = s * b + beta), record stores are contiguous per band (staged through LDS).
+__global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
+    const uint64_t *__restrict__ sig, int64_t n, int32_t M, int32_t b, int32_t r,
+    const int64_t *__restrict__ offs, int64_t R, uint64_t *__restrict__ rec, uint8_t *__restrict__ F) {
+    extern __shared__ uint32_t keyhi[];  // [b][64]
+    const int64_t i0 = (int64_t)blockIdx.x * kKeysTileSeqs;
+    const int items = kKeysTileSeqs * b;
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        int s = e / b, beta = e - s * b;
+        int64_t i = i0 + s;
+        if (i >= n) continue;
+        const uint64_t *tup = sig + i * (int64_t)M + (int64_t)beta * r;
+        uint64_t rep = R > 1 ? (uint64_t)rep_of(offs, R, i) : 0ull;
+        uint64_t h = mix64(rep * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull + (uint64_t)beta);
+        for (int k = 0; k < r; ++k) h = mix64(h ^ tup[k]);
+        keyhi[beta * kKeysTileSeqs + s] = (uint32_t)(h >> 32);
+        F[i * b + beta] = (uint8_t)h;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < items; e += blockDim.x) {
+        int beta = e / kKeysTileSeqs, s = e - beta * kKeysTileSeqs;
+        int64_t i = i0 + s;
+        if (i >= n) continue;
+        uint64_t q = (uint64_t)beta * (uint64_t)n + (uint64_t)i;
+        rec[q] = ((uint64_t)keyhi[e] << 32) | q;
+    }
+}
+
+__device__ __forceinline__ bool tuple_equal(const uint64_t *__restrict__ sig, int64_t M, int64_t i, int64_t j,
+                                            int beta, int r) {
+    const uint64_t *a = sig + i * M + (int64_t)beta * r;
+    const uint64_t *c = sig + j * M + (int64_t)beta * r;
+    bool eq = true;
+    for (int k = 0; k < r; ++k) eq &= a[k] == c[k];
+    return eq;
+}
+
+// Step 3.  One thread per sorted record; the thread walks the rest of its run.
+__global__ __launch_bounds__(kEmitThreads) void lsh_emit_kernel(
+    const uint64_t *__restrict__ srec, int64_t total, int64_t n, const uint64_t *__restrict__ sig, int32_t M,
+    int32_t b, int32_t r, const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+    uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const uint64_t me = srec[q];
+    const uint32_t hi = (uint32_t)(me >> 32);
+    const uint32_t lo = (uint32_t)me;
+    const uint32_t n32 = (uint32_t)n;
+    const int beta = (int)(lo / n32);
+    if (beta >= b) return;
+    const int64_t i = (int64_t)(lo - (uint32_t)beta * n32);
+    const int64_t rep_i = R > 1 ? rep_of(offs, R, i) : 0;
+    const uint8_t *Fi = F + i * b;
+    for (int64_t y = q + 1; y < total; ++y) {
+        const uint64_t other = srec[y];
+        if ((uint32_t)(other >> 32) != hi) break;
+        const uint32_t olo = (uint32_t)other;
+        const int obeta = (int)(olo / n32);
+        if (obeta != beta || obeta >= b) break;
+        const int64_t j = (int64_t)(olo - (uint32_t)obeta * n32);  // j > i within a run
+        if (R > 1 && rep_of(offs, R, j) != rep_i) continue;
+        if (!tuple_equal(sig, M, i, j, beta, r)) continue;
+        const uint8_t *Fj = F + j * b;
+        bool earlier = false;
+        for (int e = 0; e < beta && !earlier; ++e)
+            if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) earlier = true;
+        if (earlier) continue;
+        unsigned long long slot = atomicAdd(count, 1ull);
+        if ((int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+    }
+}
+
+__global__ void lsh_init_kernel(unsigned long long *count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0ull;
+}
+
+// Publishes P, the capacity status, and the clamped pair count used by the pair sort.
+__global__ void lsh_count_kernel(const unsigned long long *__restrict__ count, int64_t cap,
+                                 int64_t *__restrict__ n_pairs, int32_t *__restrict__ status,
+                                 int64_t *__restrict__ clamped) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int64_t P = (int64_t)*count;
+        if (n_pairs) *n_pairs = P;
+        if (status) *status = P > cap ? SUBQUAD_ERR_CAPACITY : 0;
+        *clamped = P > cap ? 0 : P;  // on overflow nothing is sorted or written
+    }
+}
+
+__global__ void lsh_pairs_kernel(const uint64_t *__restrict__ skeys, const int64_t *__restrict__ clamped,
+                                 int64_t cap, int nb, int32_t *__restrict__ pairs) {
+    const int64_t P = *clamped;
+    const uint64_t jmask = (1ull << nb) - 1ull;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t k = skeys[p];
+        pairs[2 * p] = (int32_t)(k >> nb);
+        pairs[2 * p + 1] = (int32_t)(k & jmask);
+    }
+}
+
+// row_offsets[i] = number of pairs whose first index is < i (lower bound in sorted keys).
+__global__ void lsh_rows_kernel(const uint64_t *__restrict__ skeys, const int64_t *__restrict__ clamped,
+                                int64_t n, int nb, int64_t *__restrict__ row_offsets) {
+    const int64_t P = *clamped;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t key = (uint64_t)i << nb;
+        int64_t lo = 0, hi = P;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) >> 1;
+            if (skeys[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        row_offsets[i] = lo;
+    }
+}
+
+struct LshLayout {
+    size_t rec_a, rec_b, fp, pk_a, pk_b, misc, radix, total;
+};
+
+static int bits_for(int64_t n) {
+    int nb = 1;
+    while ((int64_t(1) << nb) < n) ++nb;
+    return nb;
+}
+
+static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
+    LshLayout L{};
+    const int64_t recs = n * b;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
+    L.rec_a = take(sizeof(uint64_t) * recs);
+    L.rec_b = take(sizeof(uint64_t) * recs);
+    L.fp = take((size_t)recs);
+    L.pk_a = take(sizeof(uint64_t) * cap);
+    L.pk_b = take(sizeof(uint64_t) * cap);
+    L.misc = take(64);
+    L.radix = take(radix_scratch_bytes(std::max<int64_t>(recs, cap)));
+    L.total = off;
+    return L;
+}
+
+static int lsh_validate(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r, const int64_t *offs,
+                        int64_t R, void *ws, size_t ws_bytes, int32_t *pairs, int64_t cap) {
+    SQ_REQUIRE(n >= 0 && cap >= 0, SUBQUAD_ERR_ARG, "n and cap must be >= 0");
+    SQ_REQUIRE(b >= 1 && r >= 1 && (int64_t)b * r <= M && M <= 4096, SUBQUAD_ERR_ARG,
+               "need b >= 1, r >= 1, b*r <= M (b=%d r=%d M=%d)", b, r, M);
+    SQ_REQUIRE(n * (int64_t)b < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "n*b must be below 2^32");
+    SQ_REQUIRE(n < (int64_t(1) << 31), SUBQUAD_ERR_ARG, "n must be below 2^31");
+    SQ_REQUIRE(R >= 1 && (R == 1 || offs), SUBQUAD_ERR_ARG, "R >= 1 and rep_offsets required when R > 1");
+    SQ_REQUIRE(n == 0 || sig, SUBQUAD_ERR_ARG, "null signature pointer");
+    SQ_REQUIRE(cap == 0 || pairs, SUBQUAD_ERR_ARG, "null pairs pointer");
+    SQ_REQUIRE(ws || n == 0, SUBQUAD_ERR_ARG, "null workspace");
+    SQ_REQUIRE(((uintptr_t)ws & 255) == 0, SUBQUAD_ERR_ARG, "workspace must be 256-byte aligned");
+    size_t need = lsh_layout(n, b, cap).total;
+    SQ_REQUIRE(ws_bytes >= need, SUBQUAD_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return SUBQUAD_OK;
+}
+
+// Steps 1-3: records, sort, emission.  Leaves the raw pair keys in L.pk_a and the count in misc.
+static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r, const int64_t *offs,
+                     int64_t R, char *ws, const LshLayout &L, int64_t cap, int nb, hipStream_t st) {
+    const int64_t recs = n * b;
+    uint64_t *rec_a = reinterpret_cast<uint64_t *>(ws + L.rec_a);
+    uint64_t *rec_b = reinterpret_cast<uint64_t *>(ws + L.rec_b);
+    uint8_t *F = reinterpret_cast<uint8_t *>(ws + L.fp);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(ws + L.misc);
+    void *rscratch = ws + L.radix;
+    const size_t rscratch_bytes = radix_scratch_bytes(std::max<int64_t>(recs, cap));
+
+    lsh_init_kernel<<<1, 64, 0, st>>>(count);
+    SQ_LAUNCHED("lsh_init_kernel");
+    const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;
+    SQ_REQUIRE(lds <= 64 * 1024, SUBQUAD_ERR_ARG, "too many bands");
+    lsh_keys_kernel<<<(unsigned)ceil_div(n, kKeysTileSeqs), kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, rec_a,
+                                                                                      F);
+    SQ_LAUNCHED("lsh_keys_kernel");
+    uint64_t *sorted = nullptr;
+    int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted);
+    if (rc != SUBQUAD_OK) return rc;
+    lsh_emit_kernel<<<(unsigned)ceil_div(recs, kEmitThreads), kEmitThreads, 0, st>>>(
+        sorted, recs, n, sig, M, b, r, F, offs, R, nb, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
+    SQ_LAUNCHED("lsh_emit_kernel");
+    return SUBQUAD_OK;
+}
+
+// Step 4 on `P_host` keys (or the device count when P_host < 0, sized for cap).
+static int lsh_back(int64_t n, char *ws, const LshLayout &L, int64_t cap, int64_t sort_n, int nb, int32_t *pairs,
+                    int64_t *row_offsets, int64_t *n_pairs_dev, int32_t *status_dev, hipStream_t st) {
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(ws + L.misc);
+    int64_t *clamped = reinterpret_cast<int64_t *>(ws + L.misc + 16);
+    lsh_count_kernel<<<1, 64, 0, st>>>(count, cap, n_pairs_dev, status_dev, clamped);
+    SQ_LAUNCHED("lsh_count_kernel");
+    uint64_t *sorted = reinterpret_cast<uint64_t *>(ws + L.pk_a);
+    if (sort_n > 0) {
+        int rc = radix_sort_u64(reinterpret_cast<uint64_t *>(ws + L.pk_a), reinterpret_cast<uint64_t *>(ws + L.pk_b),
+                                sort_n, clamped, 0, 2 * nb, ws + L.radix, L.total - L.radix, st, &sorted);
+        if (rc != SUBQUAD_OK) return rc;
+        int64_t blocks = std::min<int64_t>(ceil_div(sort_n, 256), (int64_t)device_cus() * 16);
+        lsh_pairs_kernel<<<(unsigned)blocks, 256, 0, st>>>(sorted, clamped, cap, nb, pairs);
+        SQ_LAUNCHED("lsh_pairs_kernel");
+    }
+    if (row_offsets) {
+        int64_t blocks = std::min<int64_t>(ceil_div(n + 1, 256), (int64_t)device_cus() * 16);
+        lsh_rows_kernel<<<(unsigned)blocks, 256, 0, st>>>(sorted, clamped, n, nb, row_offsets);
+        SQ_LAUNCHED("lsh_rows_kernel");
+    }
+    return SUBQUAD_OK;
+}
+
+}  // namespace subquad
+
+using namespace subquad;
+
+extern "C" size_t subquad_lsh_workspace_bytes(int64_t n, int32_t b, int64_t cap) {
+    if (n < 0 || b < 1 || cap < 0 || n * (int64_t)b >= (int64_t(1) << 32)) return 0;
+    return lsh_layout(n, b, cap).total;
+}
+
+extern "C" int subquad_lsh_candidates(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r,
+                                      const int64_t *rep_offsets, int64_t R, void *ws, size_t ws_bytes,
+                                      int32_t *pairs, int64_t *row_offsets, int64_t cap, int64_t *n_pairs,
+                                      void *stream) {
+    clear_error();
+    SQ_REQUIRE(n_pairs, SUBQUAD_ERR_ARG, "null n_pairs");
+    int rc = lsh_validate(sig, n, M, b, r, rep_offsets, R, ws, ws_bytes, pairs, cap);
+    if (rc != SUBQUAD_OK) return rc;
+    *n_pairs = 0;
+    hipStream_t st = as_stream(stream);
+    const LshLayout L = lsh_layout(n, b, cap);
+    char *w = static_cast<char *>(ws);
+    if (n == 0) {
+        if (row_offsets) SQ_HIP(hipMemsetAsync(row_offsets, 0, sizeof(int64_t), st));
+        return SUBQUAD_OK;
+    }
+    const int nb = bits_for(n);
+    rc = lsh_front(sig, n, M, b, r, rep_offsets, R, w, L, cap, nb, st);
+    if (rc != SUBQUAD_OK) return rc;
+    unsigned long long P = 0;
+    SQ_HIP(hipMemcpyAsync(&P, w + L.misc, sizeof(P), hipMemcpyDeviceToHost, st));
+    SQ_HIP(hipStreamSynchronize(st));
+    *n_pairs = (int64_t)P;
+    SQ_REQUIRE((int64_t)P <= cap, SUBQUAD_ERR_CAPACITY, "%llu candidate pairs exceed the capacity %lld", P,
+               (long long)cap);
+    return lsh_back(n, w, L, cap, (int64_t)P, nb, pairs, row_offsets, nullptr, nullptr, st);
+}
+
+extern "C" int subquad_lsh_candidates_async(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r,
+                                            const int64_t *rep_offsets, int64_t R, void *ws, size_t ws_bytes,
+                                            int32_t *pairs, int64_t *row_offsets, int64_t cap, int64_t *n_pairs_dev,
+                                            int32_t *status_dev, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n_pairs_dev && status_dev, SUBQUAD_ERR_ARG, "null device count or status pointer");
+    int rc = lsh_validate(sig, n, M, b, r, rep_offsets, R, ws, ws_bytes, pairs, cap);
+    if (rc != SUBQUAD_OK) return rc;
+    SQ_REQUIRE(n > 0, SUBQUAD_ERR_ARG, "the asynchronous variant needs n > 0");
+    hipStream_t st = as_stream(stream);
+    const LshLayout L = lsh_layout(n, b, cap);
+    char *w = static_cast<char *>(ws);
+    const int nb = bits_for(n);
+    rc = lsh_front(sig, n, M, b, r, rep_offsets, R, w, L, cap, nb, st);
+    if (rc != SUBQUAD_OK) return rc;
+    return lsh_back(n, w, L, cap, cap, nb, pairs, row_offsets, n_pairs_dev, status_dev, st);
+}

@@ -1,0 +1,244 @@
+// Device-wide stable LSD radix sort of 64-bit records (8-bit digits) and exclusive scan.
+//
+// Each pass is three launches: a per-tile digit histogram, an exclusive scan of the
+// digit-major histogram (so tile t's bucket d starts after every earlier tile's bucket d and
+// every smaller bucket), and a scatter.  The scatter ranks records stably inside a tile
+// with wave ballots (the eight digit bits give each lane the mask of lanes holding the same
+// digit; its rank is the popcount of the lower lanes in that mask) and per-wave digit
+// counters in LDS, stages the tile in LDS in sorted order, and then writes each digit's run
+// with consecutive threads so that global stores are contiguous.
+#include "radix.h"
+
+namespace subquad {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Inclusive scan of one value per thread over a block of kScanThreads (= 4 waves).
+__device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *wave_tot) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) wave_tot[w] = v;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int k = 0; k < w; ++k) add += wave_tot[k];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ data,
+                                                                   int64_t count, uint32_t *__restrict__ partial) {
+    __shared__ uint32_t wt[4];
+    int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (idx < count) s += data[idx];
+    }
+    uint32_t inc = block_inclusive_scan(s, wt);
+    if (threadIdx.x == kScanThreads - 1) partial[blockIdx.x] = inc;
+}
+
+// Single block: exclusive scan of the chunk totals, any length.
+__global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *__restrict__ partial, int64_t m) {
+    __shared__ uint32_t wt[4];
+    __shared__ uint32_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < m; base += kScanThreads) {
+        int64_t idx = base + threadIdx.x;
+        uint32_t v = idx < m ? partial[idx] : 0;
+        uint32_t inc = block_inclusive_scan(v, wt);
+        uint32_t carry = carry_s;
+        if (idx < m) partial[idx] = carry + inc - v;
+        __syncthreads();
+        if (threadIdx.x == kScanThreads - 1) carry_s = carry + inc;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ data, int64_t count,
+                                                                  const uint32_t *__restrict__ partial) {
+    __shared__ uint32_t wt[4];
+    // thread t owns kScanItems consecutive entries
+    int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        v[k] = idx < count ? data[idx] : 0;
+        s += v[k];
+    }
+    uint32_t inc = block_inclusive_scan(s, wt);
+    uint32_t run = partial[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        if (idx < count) data[idx] = run;
+        run += v[k];
+    }
+}
+
+size_t scan_scratch_bytes(int64_t count) {
+    return align_up(sizeof(uint32_t) * (size_t)std::max<int64_t>(1, ceil_div(count, kScanChunk)), 256);
+}
+
+int scan_exclusive_u32(uint32_t *data, int64_t count, void *scratch, hipStream_t st) {
+    if (count <= 0) return SUBQUAD_OK;
+    int64_t chunks = ceil_div(count, kScanChunk);
+    uint32_t *partial = static_cast<uint32_t *>(scratch);
+    scan_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial);
+    SQ_LAUNCHED("scan_reduce_kernel");
+    scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks);
+    SQ_LAUNCHED("scan_partials_kernel");
+    scan_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial);
+    SQ_LAUNCHED("scan_apply_kernel");
+    return SUBQUAD_OK;
+}
+
+__device__ __forceinline__ int64_t live_count(int64_t n_cap, const int64_t *n_dev) {
+    if (!n_dev) return n_cap;
+    int64_t v = *n_dev;
+    return v < n_cap ? (v < 0 ? 0 : v) : n_cap;
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_t *__restrict__ in, int64_t n_cap,
+                                                                   const int64_t *__restrict__ n_dev, int shift,
+                                                                   uint32_t dmask, uint32_t *__restrict__ hist,
+                                                                   int64_t nblocks) {
+    __shared__ uint32_t h[kRadixBuckets];
+    const int64_t n = live_count(n_cap, n_dev);
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    if (base < n) {
+#pragma unroll 4
+        for (int k = 0; k < kRadixItems; ++k) {
+            int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
+            if (idx < n) atomicAdd(&h[(uint32_t)(in[idx] >> shift) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
+    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n_cap, const int64_t *__restrict__ n_dev,
+    int shift, uint32_t dmask, const uint32_t *__restrict__ hist, int64_t nblocks) {
+    constexpr int kWaves = kRadixThreads / 64;
+    __shared__ uint32_t wc[kWaves][kRadixBuckets];
+    __shared__ uint32_t tile_off[kRadixBuckets];
+    __shared__ uint32_t gbase[kRadixBuckets];
+    __shared__ uint32_t wt[4];
+    __shared__ uint64_t stage[kRadixTile];
+
+    const int64_t n = live_count(n_cap, n_dev);
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    if (tile0 >= n) return;  // whole block
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int k = t; k < kWaves * kRadixBuckets; k += kRadixThreads) (&wc[0][0])[k] = 0;
+    __syncthreads();
+
+    const int64_t base = tile0 + (int64_t)w * (64 * kRadixItems);
+    const uint64_t lt = lanemask_lt(lane);
+    uint64_t rec[kRadixItems];
+    uint32_t rank[kRadixItems];
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        int64_t idx = base + (int64_t)k * 64 + lane;
+        bool valid = idx < n;
+        rec[k] = valid ? in[idx] : 0ull;
+        uint32_t d = (uint32_t)(rec[k] >> shift) & dmask;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < kRadixBits; ++bit) {
+            bool on = (d >> bit) & 1u;
+            uint64_t bal = __ballot(on);
+            m &= on ? bal : ~bal;
+        }
+        uint32_t r = 0;
+        if (valid) {
+            uint32_t before = wc[w][d];
+            r = before + (uint32_t)__popcll(m & lt);
+            if ((m & lt) == 0) wc[w][d] = before + (uint32_t)__popcll(m);
+        }
+        rank[k] = valid ? r : 0xFFFFFFFFu;
+    }
+    __syncthreads();
+    // wave-exclusive offsets per digit, then the tile-exclusive digit offsets
+    uint32_t tot = 0;
+    {
+        const int d = t;  // kRadixThreads == kRadixBuckets
+#pragma unroll
+        for (int ww = 0; ww < kWaves; ++ww) {
+            uint32_t c = wc[ww][d];
+            wc[ww][d] = tot;
+            tot += c;
+        }
+        gbase[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+    }
+    uint32_t inc = block_inclusive_scan(tot, wt);
+    tile_off[t] = inc - tot;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        if (rank[k] != 0xFFFFFFFFu) {
+            uint32_t d = (uint32_t)(rec[k] >> shift) & dmask;
+            stage[tile_off[d] + wc[w][d] + rank[k]] = rec[k];
+        }
+    }
+    __syncthreads();
+    const int tile_n = (int)std::min<int64_t>(kRadixTile, n - tile0);
+    for (int s = t; s < tile_n; s += kRadixThreads) {
+        uint64_t v = stage[s];
+        uint32_t d = (uint32_t)(v >> shift) & dmask;
+        const int64_t pos = (int64_t)gbase[d] + (s - (int64_t)tile_off[d]);
+        if (pos >= 0 && pos < n) out[pos] = v;
+    }
+}
+
+size_t radix_scratch_bytes(int64_t n_cap) {
+    int64_t nblocks = std::max<int64_t>(1, ceil_div(n_cap, kRadixTile));
+    int64_t hist = nblocks * kRadixBuckets;
+    return align_up(sizeof(uint32_t) * (size_t)hist, 256) + scan_scratch_bytes(hist);
+}
+
+int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev, int lo_bit, int key_bits,
+                   void *scratch, size_t scratch_bytes, hipStream_t st, uint64_t **result) {
+    *result = a;
+    if (n_cap <= 1 || key_bits <= 0) return SUBQUAD_OK;
+    SQ_REQUIRE(scratch_bytes >= radix_scratch_bytes(n_cap), SUBQUAD_ERR_WORKSPACE, "radix scratch too small");
+    const int64_t nblocks = ceil_div(n_cap, kRadixTile);
+    const int64_t hist_n = nblocks * kRadixBuckets;
+    SQ_REQUIRE(n_cap < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "radix sort limited to 2^32 records");
+    uint32_t *hist = static_cast<uint32_t *>(scratch);
+    void *scan_scratch = static_cast<char *>(scratch) + align_up(sizeof(uint32_t) * (size_t)hist_n, 256);
+    uint64_t *src = a, *dst = b;
+    for (int done = 0; done < key_bits; done += kRadixBits) {
+        const int bits = std::min(kRadixBits, key_bits - done);
+        const int shift = lo_bit + done;
+        const uint32_t dmask = (1u << bits) - 1u;
+        radix_hist_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask, hist, nblocks);
+        SQ_LAUNCHED("radix_hist_kernel");
+        int rc = scan_exclusive_u32(hist, hist_n, scan_scratch, st);
+        if (rc != SUBQUAD_OK) return rc;
+        radix_scatter_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift, dmask, hist,
+                                                                          nblocks);
+        SQ_LAUNCHED("radix_scatter_kernel");
+        std::swap(src, dst);
+    }
+    *result = src;
+    return SUBQUAD_OK;
+}
+
+}  // namespace subquad

@@ -1,0 +1,155 @@
+"""GPU gate forward/backward against the float64 oracle.
+
+Tolerances (float32 kernels against float64): fused |f - f64| <= 1e-5 |f64| + 1e-6; gradients
+normwise ||d|| <= 1e-5 ||ref|| and per element |d| <= 1e-5 |ref| + 1e-6 max|ref|."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_17330_amd as sq
+import synth
+from helpers import dev, fused_tol_ok, grad_tol_ok, say, sw_oracle, workload
+from oracle import gate as ogate
+from oracle import sw as osw
+
+pytestmark = pytest.mark.gpu
+
+
+def make_case(rep, d, H, P, seed, same_frac=0.5, scale_norms=False, gseed=77):
+    S = synth.load_blosum62()
+    emb = synth.embeddings(rep.seqs, rep.lens, d)
+    if scale_norms:
+        rng = np.random.default_rng(seed)
+        emb = (emb * rng.uniform(0.25, 4.0, (rep.n, 1))).astype(np.float32)
+    pairs = synth.random_pairs(rep.n, P, seed, family=rep.family, same_frac=same_frac)
+    align = sw_oracle(rep.seqs, rep.lens, pairs, S)
+    self_s = osw.self_scores(rep.seqs, rep.lens, S)
+    W1, b1, w2, b2 = synth.gate_params(H, seed=gseed)
+    return dict(emb=emb, lens=rep.lens, vgene=rep.vgene, self_scores=self_s, pairs=pairs, align=align,
+                W1=W1, b1=b1, w2=w2, b2=b2, family=rep.family)
+
+
+def gpu_args(c):
+    return (dev(c["emb"]), dev(c["lens"]), dev(c["vgene"]), dev(c["self_scores"]), dev(c["pairs"]),
+            dev(c["align"]), dev(c["W1"]), dev(c["b1"]), dev(c["w2"]), dev(c["b2"]))
+
+
+def oracle_args(c):
+    return dict((k, c[k]) for k in ("emb", "lens", "vgene", "self_scores", "pairs", "align", "W1", "b1",
+                                    "w2", "b2"))
+
+
+@pytest.mark.parametrize("d,H", [(64, 64), (128, 64), (4, 16), (100, 32), (256, 128), (1024, 256), (128, 16)])
+def test_forward(d, H):
+    rep = synth.tiny(n_families=60, fam_size=8, seed=d + H)
+    c = make_case(rep, d, H, 3000, seed=d, scale_norms=True)
+    say(f"gate fwd d={d} H={H}")
+    f, g = sq.gate_fwd(*gpu_args(c), return_gate=True)
+    torch.cuda.synchronize()
+    ref, inter = ogate.forward(**oracle_args(c), return_all=True)
+    ok, err = fused_tol_ok(f.cpu().numpy(), ref)
+    assert ok, err
+    assert np.allclose(g.cpu().numpy(), inter["g"], rtol=1e-5, atol=1e-6)
+
+
+@pytest.mark.parametrize("d,H", [(64, 64), (128, 64), (100, 32), (256, 128), (4, 16)])
+def test_backward(d, H):
+    rep = synth.tiny(n_families=60, fam_size=8, seed=d * 3 + H)
+    c = make_case(rep, d, H, 3000, seed=d + 1, scale_norms=True)
+    gf = synth.upstream_grad(c["pairs"].shape[0], seed=d)
+    say(f"gate bwd d={d} H={H}")
+    grads = sq.gate_bwd(*gpu_args(c), dev(gf))
+    torch.cuda.synchronize()
+    ref = ogate.backward(**oracle_args(c), grad_f=gf)
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
+        assert ok, (name, rel)
+
+
+def test_backward_accumulates_and_skips_emb():
+    rep = synth.tiny(seed=5)
+    c = make_case(rep, 64, 64, 1000, seed=2)
+    gf = synth.upstream_grad(c["pairs"].shape[0], seed=1)
+    say("gate bwd accumulate")
+    g1 = sq.gate_bwd(*gpu_args(c), dev(gf))
+    g2 = sq.gate_bwd(*gpu_args(c), dev(gf), grads=tuple(x.clone() for x in g1))
+    g3 = sq.gate_bwd(*gpu_args(c), dev(gf), need_emb=False)
+    torch.cuda.synchronize()
+    for a, b in zip(g1, g2):
+        assert torch.allclose(2 * a, b, rtol=1e-6, atol=1e-7)
+    for a, b in zip(g1[:4], g3[:4]):
+        assert torch.allclose(a, b, rtol=1e-6, atol=1e-7)
+    assert g3[4] is None
+
+
+def test_gatefn_autograd_and_loss():
+    rep = synth.tiny(seed=6)
+    c = make_case(rep, 64, 64, 2000, seed=3)
+    y = (c["family"][c["pairs"][:, 0]] == c["family"][c["pairs"][:, 1]]).astype(np.float64)
+    say("GateFn autograd")
+    emb = dev(c["emb"]).requires_grad_(True)
+    W = [dev(c[k]).requires_grad_(True) for k in ("W1", "b1", "w2", "b2")]
+    f = sq.GateFn.apply(emb, *W, dev(c["pairs"]), dev(c["align"]), dev(c["self_scores"]), dev(c["lens"]),
+                        dev(c["vgene"]))
+    yt = torch.as_tensor(y, dtype=torch.float32, device="cuda")
+    hinge = torch.clamp(f - ogate.MARGIN, min=0)
+    loss = (yt * (1 - f) ** 2 + (1 - yt) * hinge ** 2).mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    f64 = ogate.forward(**oracle_args(c))
+    _, gl = ogate.contrastive_loss(f64, y)
+    ref = ogate.backward(**oracle_args(c), grad_f=gl)
+    for name, t in zip(("emb", "W1", "b1", "w2", "b2"), (emb, *W)):
+        ok, rel = grad_tol_ok(t.grad.cpu().numpy(), ref[name], rel=2e-5)
+        assert ok, (name, rel)
+
+
+def test_zero_norm_embedding():
+    rep = synth.tiny(seed=8)
+    c = make_case(rep, 64, 64, 500, seed=4)
+    c["emb"] = c["emb"].copy()
+    zero_rows = np.unique(c["pairs"][:20, 1])
+    c["emb"][zero_rows] = 0.0
+    gf = synth.upstream_grad(c["pairs"].shape[0], seed=4)
+    say("gate zero-norm embeddings")
+    f = sq.gate_fwd(*gpu_args(c))
+    grads = sq.gate_bwd(*gpu_args(c), dev(gf))
+    torch.cuda.synchronize()
+    ref = ogate.forward(**oracle_args(c))
+    ok, err = fused_tol_ok(f.cpu().numpy(), ref)
+    assert ok, err
+    rb = ogate.backward(**oracle_args(c), grad_f=gf)
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        assert np.isfinite(g.cpu().numpy()).all()
+        ok, rel = grad_tol_ok(g.cpu().numpy(), rb[name])
+        assert ok, (name, rel)
+
+
+def test_pair_symmetry_and_empty():
+    rep = synth.tiny(seed=9)
+    c = make_case(rep, 64, 64, 500, seed=5)
+    say("gate symmetry / empty")
+    f1 = sq.gate_fwd(*gpu_args(c)).cpu().numpy()
+    c2 = dict(c, pairs=np.ascontiguousarray(c["pairs"][:, ::-1]))
+    f2 = sq.gate_fwd(*gpu_args(c2)).cpu().numpy()
+    assert np.allclose(f1, f2, rtol=1e-6, atol=1e-7)
+    c3 = dict(c, pairs=np.zeros((0, 2), np.int32), align=np.zeros(0, np.int32))
+    assert sq.gate_fwd(*gpu_args(c3)).shape == (0,)
+
+
+def test_gate_2p20_pairs_full_size():
+    """Training workload: 2^20 family-heavy pairs of the 100k Zipf repertoire, d=128, H=64,
+    forward and backward against the float64 oracle over every pair."""
+    rep = workload("zipf100k")
+    c = make_case(rep, 128, 64, 1 << 20, seed=1004, same_frac=0.7)
+    gf = synth.upstream_grad(c["pairs"].shape[0], seed=1004)
+    say(f"gate 2^20 pairs P={c['pairs'].shape[0]}")
+    f = sq.gate_fwd(*gpu_args(c))
+    grads = sq.gate_bwd(*gpu_args(c), dev(gf))
+    torch.cuda.synchronize()
+    ref = ogate.backward(**oracle_args(c), grad_f=gf)
+    ok, err = fused_tol_ok(f.cpu().numpy(), ref["f"])
+    assert ok, err
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
+        assert ok, (name, rel)

@@ -1,0 +1,103 @@
+"""The whole hot path end to end (MinHash -> LSH -> Smith-Waterman -> gate forward and
+backward) against the oracle chain, batching over repertoires, and determinism."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2602_17330_amd as sq
+import synth
+from helpers import dev, fused_tol_ok, grad_tol_ok, host_u64, say, sw_oracle, workload
+from oracle import gate as ogate
+from oracle import lsh as olsh
+from oracle import minhash as omh
+from oracle import sw as osw
+
+pytestmark = pytest.mark.gpu
+
+
+def run_gpu(rep, S, emb, W, gf_seed=5):
+    p = rep.params
+    seqs, lens = dev(rep.seqs), dev(rep.lens)
+    offs = dev(rep.rep_offsets) if len(rep.rep_offsets) > 2 else None
+    sig = sq.minhash(seqs, lens, p["M"])
+    pairs, rows = sq.lsh_candidates(sig, p["b"], p["r"], rep_offsets=offs)
+    St = dev(S)
+    scores = sq.align(seqs, lens, pairs, St)
+    self_s = sq.self_scores(seqs, lens, St)
+    args = (dev(emb), lens, dev(rep.vgene), self_s, pairs, scores, *[dev(w) for w in W])
+    fused = sq.gate_fwd(*args)
+    gf = dev(synth.upstream_grad(pairs.shape[0], seed=gf_seed))
+    grads = sq.gate_bwd(*args, gf)
+    torch.cuda.synchronize()
+    return dict(sig=host_u64(sig), pairs=pairs.cpu().numpy().astype(np.int64), rows=rows.cpu().numpy(),
+                scores=scores.cpu().numpy(), fused=fused.cpu().numpy(),
+                grads=[g.cpu().numpy() for g in grads])
+
+
+def test_small5k_end_to_end():
+    rep = workload("small5k")
+    S = synth.load_blosum62()
+    p = rep.params
+    emb = synth.embeddings(rep.seqs, rep.lens, p["d"])
+    W = synth.gate_params(64)
+    say("pipeline small5k")
+    got = run_gpu(rep, S, emb, W)
+    sig = omh.signatures(rep.seqs, rep.lens, p["M"], synth.HASH_SEED)
+    assert np.array_equal(got["sig"], sig)
+    pairs = olsh.candidates(sig, p["b"], p["r"])
+    assert np.array_equal(got["pairs"], pairs)
+    scores = osw.scores_pairs(rep.seqs, rep.lens, pairs, S)
+    assert np.array_equal(got["scores"], scores)
+    self_s = osw.self_scores(rep.seqs, rep.lens, S)
+    oa = dict(emb=emb, lens=rep.lens, vgene=rep.vgene, self_scores=self_s, pairs=pairs, align=scores,
+              W1=W[0], b1=W[1], w2=W[2], b2=W[3])
+    gf = synth.upstream_grad(pairs.shape[0], seed=5)
+    ref = ogate.backward(**oa, grad_f=gf)
+    ok, err = fused_tol_ok(got["fused"], ref["f"])
+    assert ok, err
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), got["grads"]):
+        ok, rel = grad_tol_ok(g, ref[name])
+        assert ok, (name, rel)
+
+
+def test_batched_equals_per_repertoire():
+    batch = synth.batch64(R=12, scale=0.004)
+    S = synth.load_blosum62()
+    emb = synth.embeddings(batch.seqs, batch.lens, 128)
+    W = synth.gate_params(64)
+    say(f"pipeline batch R=12 n={batch.n}")
+    got = run_gpu(batch, S, emb, W)
+    offs = batch.rep_offsets
+    parts_pairs, parts_scores, parts_fused = [], [], []
+    for k in range(len(offs) - 1):
+        lo, hi = offs[k], offs[k + 1]
+        sub = synth.Repertoire(name="part", seqs=batch.seqs[lo:hi], lens=batch.lens[lo:hi],
+                               family=batch.family[lo:hi], vgene=batch.vgene[lo:hi],
+                               subgroup=batch.subgroup[lo:hi], rep_offsets=np.array([0, hi - lo]),
+                               params=batch.params)
+        g = run_gpu(sub, S, emb[lo:hi], W)
+        parts_pairs.append(g["pairs"] + lo)
+        parts_scores.append(g["scores"])
+        parts_fused.append(g["fused"])
+    assert np.array_equal(got["pairs"], np.concatenate(parts_pairs))
+    assert np.array_equal(got["scores"], np.concatenate(parts_scores))
+    assert np.allclose(got["fused"], np.concatenate(parts_fused), rtol=1e-6, atol=1e-7)
+    # and against the oracle on the whole batch
+    sig = omh.signatures(batch.seqs, batch.lens, 128, synth.HASH_SEED)
+    assert np.array_equal(got["sig"], sig)
+    assert np.array_equal(got["pairs"], olsh.candidates_grouped(sig, 32, 4, rep_offsets=offs))
+
+
+def test_two_runs_identical():
+    rep = workload("small5k")
+    S = synth.load_blosum62()
+    emb = synth.embeddings(rep.seqs, rep.lens, 64)
+    W = synth.gate_params(64)
+    say("pipeline determinism")
+    a = run_gpu(rep, S, emb, W)
+    b = run_gpu(rep, S, emb, W)
+    for k in ("sig", "pairs", "rows", "scores", "fused"):
+        assert np.array_equal(a[k], b[k]), k
+    for x, y in zip(a["grads"][:4], b["grads"][:4]):
+        assert np.array_equal(x, y)
+    assert np.allclose(a["grads"][4], b["grads"][4], rtol=1e-5, atol=1e-7)
