@@ -1,0 +1,291 @@
+"""Benchmark of the SubQuad hot path on one MI355X.
+
+A step is one pass of the whole path over one batch: MinHash signatures -> LSH candidate
+pairs -> self-scores -> Smith-Waterman on every candidate -> gated fusion forward ->
+(contrastive loss gradient) -> gated fusion backward.  The default workload is the
+1,000,000-sequence repertoire (lengths 8-20, 100,000 families, M = 128, 32 x 4 bands,
+d = 128, H = 64), inputs resident in HBM before timing.
+
+Prints one JSON line.  ``value`` is whole-step throughput in GCUPS: candidate
+dynamic-programming cells (sum of L_i * L_j over candidate pairs) per second of the whole
+step.  The Smith-Waterman kernel's own GCUPS, the per-stage times, the gated-fusion
+forward+backward rate on 2^20 pairs, the dominant kernel's roofline and the CPU oracle's
+rate on a bounded sample are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# int32 VALU lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+SW_OPS_PER_CELL = 8  # int32 VALU operations of one Gotoh cell update
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rep1m", choices=["rep1m", "zipf100k", "small5k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="also run N device copies of 1 GiB (counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    import synth
+    rep = getattr(synth, name)()
+    emb = synth.embeddings(rep.seqs, rep.lens, rep.params["d"])
+    return rep, emb
+
+
+def time_region(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def gate_2p20(torch, sq, steps, warmup):
+    """Gate forward+backward on 2^20 pairs drawn from the 100k-sequence Zipf repertoire's
+    candidates (seed 1004), sorted by (i, j); d = 128, H = 64."""
+    import synth
+    from paper_2602_17330_amd import api
+    rep = synth.zipf100k()
+    emb = synth.embeddings(rep.seqs, rep.lens, 128)
+    S = synth.load_blosum62()
+    seqs, lens = api.to_device(rep.seqs), api.to_device(rep.lens)
+    sig = sq.minhash(seqs, lens, 128)
+    pairs, _ = sq.lsh_candidates(sig, 32, 4)
+    Pall = pairs.shape[0]
+    rng = np.random.Generator(np.random.PCG64(1004))
+    pick = np.sort(rng.choice(Pall, size=min(1 << 20, Pall), replace=False))
+    pairs = pairs[torch.from_numpy(pick).cuda()].contiguous()
+    St = api.to_device(S)
+    align = sq.align(seqs, lens, pairs, St)
+    self_s = sq.self_scores(seqs, lens, St)
+    W = [api.to_device(w) for w in synth.gate_params(64)]
+    E = api.to_device(emb)
+    vg = api.to_device(rep.vgene)
+    fam = api.to_device(rep.family)
+    pr = pairs.long()
+    y = (fam[pr[:, 0]] == fam[pr[:, 1]]).float()
+    args = (E, lens, vg, self_s, pairs, align, *W)
+    fused = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
+    grads = [torch.zeros_like(w) for w in W] + [torch.zeros_like(E)]
+    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    P = pairs.shape[0]
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    fwd_ms, bwd_ms = [], []
+
+    def one(record=False):
+        if record:
+            ev[0].record()
+        sq.gate_fwd(*args, out=fused)
+        if record:
+            ev[1].record()
+        hinge = torch.clamp(fused - 0.5, min=0.0)
+        gf = (-2.0 * y * (1 - fused) + 2.0 * (1 - y) * hinge) / P
+        for g in grads:
+            g.zero_()
+        if record:
+            ev[2].record()
+        sq.gate_bwd(*args, gf, grads=tuple(grads), ws=ws)
+        if record:
+            ev[3].record()
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one(record=True)
+        torch.cuda.synchronize()
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        bwd_ms.append(ev[2].elapsed_time(ev[3]))
+    wall = (time.perf_counter() - t0) / steps
+    f_ms, b_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
+    return dict(pairs=P, candidates_total=int(Pall), fwd_ms=f_ms, bwd_ms=b_ms,
+                pairs_per_s_kernels=P / ((f_ms + b_ms) / 1e3),
+                pairs_per_s_step=P / wall, step_ms=wall * 1e3,
+                fwd_eff_GBs=P * 1040 / (f_ms / 1e3) / 1e9, bwd_eff_GBs=P * 2064 / (b_ms / 1e3) / 1e9,
+                workload="2^20 pairs sampled from the candidates of the 100,000-sequence Zipf "
+                         "repertoire, d=128, H=64, fp32")
+
+
+def cpu_baseline(rep, emb, S, pipe, cfg):
+    """The oracle, untouched, on a bounded sample of the same workload; each stage's time
+    is scaled linearly to the full workload (per sequence, per cell, per pair)."""
+    from oracle import gate as ogate
+    from oracle import lsh as olsh
+    from oracle import minhash as omh
+    from oracle import sw as osw
+    import synth
+    cores = min(16, len(os.sched_getaffinity(0)))
+    n = rep.n
+    ns = min(n, 100_000)
+    rows = np.arange(ns)
+    t = time.perf_counter()
+    sig_s = omh.signatures_c(rep.seqs[rows], rep.lens[rows], cfg.M, synth.HASH_SEED)
+    t_mh = (time.perf_counter() - t) * n / ns
+    t = time.perf_counter()
+    olsh.candidates_grouped(sig_s, cfg.b, cfg.r)
+    t_lsh = (time.perf_counter() - t) * n / ns
+    P = pipe.P
+    pairs = pipe.pairs[:P].cpu().numpy()
+    Ps = min(P, 300_000)
+    sel = synth.sample_rows(P, Ps, 3)
+    ps = pairs[sel]
+    cells_s = int((rep.lens[ps[:, 0]].astype(np.int64) * rep.lens[ps[:, 1]]).sum())
+    t = time.perf_counter()
+    al = osw.scores_pairs_parallel(rep.seqs, rep.lens, ps, S, cfg.gap_open, cfg.gap_extend, procs=cores)
+    t_sw_s = time.perf_counter() - t
+    cells = pipe.cells()
+    t_sw = t_sw_s * cells / max(cells_s, 1)
+    self_s = osw.self_scores(rep.seqs, rep.lens, S)
+    W1, b1, w2, b2 = synth.gate_params(64)
+    Pg = min(P, 100_000)
+    pg = ps[:Pg]
+    gf = synth.upstream_grad(Pg)
+    t = time.perf_counter()
+    ogate.backward(emb, rep.lens, rep.vgene, self_s, pg, al[:Pg], W1, b1, w2, b2, gf)
+    t_gate = (time.perf_counter() - t) * P / Pg
+    total = t_mh + t_lsh + t_sw + t_gate
+    return dict(value=cells / total / 1e9, unit="GCUPS", cores=cores, kind="oracle",
+                sample=f"MinHash (C) and LSH (numpy) on the first {ns} sequences, Smith-Waterman (C, "
+                       f"{cores} processes) on {Ps} sampled candidate pairs, gate fwd+bwd (numpy fp64) on "
+                       f"{Pg} pairs; each stage scaled linearly to the full workload",
+                stage_s=dict(minhash=t_mh, lsh=t_lsh, align=t_sw, gate=t_gate),
+                sw_gcups=cells / t_sw / 1e9)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
+                                   "part of this build", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2602_17330_amd as sq
+    from paper_2602_17330_amd.pipeline import STAGES, PathConfig, Pipeline
+    import synth
+
+    sq.lib()  # fails loudly if the library is missing
+    log(f"building workload {a.workload}")
+    rep, emb = build_workload(a.workload)
+    S = synth.load_blosum62()
+    p = rep.params
+    cfg = PathConfig(M=p["M"], b=p["b"], r=p["r"])
+    W = synth.gate_params(64)
+    pipe = Pipeline(rep.seqs, rep.lens, rep.vgene, rep.family, emb, S, *W, cfg=cfg,
+                    rep_offsets=rep.rep_offsets)
+    log("first pass (sizes the candidate buffers)")
+    pipe.step()
+    torch.cuda.synchronize()
+    P = pipe.P
+    cells = pipe.cells()
+    log(f"P={P} cells={cells}")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
+    stage_ms = np.zeros(len(STAGES))
+    for _ in range(a.warmup):
+        pipe.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ev[0].record()
+        pipe.step(events=ev[1:])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / a.steps
+    # event timings come from the last step only plus a separate pass below
+    per = np.zeros(len(STAGES))
+    reps = max(3, min(a.steps, 10))
+    for _ in range(reps):
+        ev[0].record()
+        pipe.step(events=ev[1:])
+        torch.cuda.synchronize()
+        per += np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(len(STAGES))])
+    stage_ms = per / reps
+    log(f"step {wall * 1e3:.3f} ms; stages " + ", ".join(f"{s}={m:.3f}" for s, m in zip(STAGES, stage_ms)))
+
+    n = rep.n
+    M, b, d = cfg.M, cfg.b, emb.shape[1]
+    bytes_alg = {
+        "minhash": n * (rep.stride + 4) + n * M * 8,
+        "gate_fwd": P * (2 * d * 4 + 8 + 4 + 4),
+        "gate_bwd": P * (2 * d * 4 + 2 * d * 4 + 8 + 4 + 4 + 4),
+        "lsh": n * b * cfg.r * 8 + 8 * P,
+    }
+    sidx = {s: k for k, s in enumerate(STAGES)}
+    rooflines = {}
+    for s, by in bytes_alg.items():
+        t = stage_ms[sidx[s]] / 1e3
+        ach = by / t / 1e9
+        rooflines[s] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                            alg_bytes=by, ms=stage_ms[sidx[s]])
+    t_al = stage_ms[sidx["align"]] / 1e3
+    ops = cells * SW_OPS_PER_CELL / t_al / 1e12
+    rooflines["align"] = dict(bound="alu", achieved=ops, peak=ALU_PEAK_TOPS, unit="Tops/s", frac=ops / ALU_PEAK_TOPS,
+                              gcups=cells / t_al / 1e9, ms=stage_ms[sidx["align"]])
+    dominant = max(rooflines, key=lambda s: rooflines[s]["ms"])
+    roof = dict(rooflines[dominant], kernel=dominant, traffic=None)
+
+    gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
+    if a.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(a.calib_copy):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    cpu = None if a.no_cpu_baseline else cpu_baseline(rep, emb, S, pipe, cfg)
+
+    out = {
+        "metric": "SW GCUPS on LSH candidates at 1M CDR3s; gated-fusion fwd+bwd pairs/sec",
+        "value": cells / wall / 1e9,
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {n} synthetic CDR3s, lengths {p['Lmin']}-{p['Lmax']}, "
+                               f"M={M}, {b}x{cfg.r} bands, BLOSUM62 gaps 10/1, d={d}, H=64; step = MinHash + "
+                               f"LSH + Smith-Waterman + gate fwd + loss grad + gate bwd",
+                   "n": n, "candidates": P, "cells": cells, "parallelism": "single GPU"},
+        "sw_kernel_gcups": rooflines["align"]["gcups"],
+        "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
+        "gate_2p20": gate,
+        "roofline": roof,
+        "rooflines": rooflines,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -45,7 +45,8 @@ def embeddings(seqs: np.ndarray, lens: np.ndarray, d: int, seed: int = 4242,
         codes = torch.from_numpy(_shingle_codes(seqs[lo:hi], lens[lo:hi])).to(device)
         v = torch.nn.functional.embedding_bag(codes, R, mode="sum", padding_idx=N_3MERS)
         ss = (v.double() ** 2).sum(1, keepdim=True)
-        out[lo:hi] = (v.double() / torch.sqrt(ss)).float()
+        # a zero projection (possible for small d) stays the zero vector
+        out[lo:hi] = (v.double() / torch.sqrt(torch.where(ss > 0, ss, torch.ones_like(ss)))).float()
     return out.numpy() if device == "cpu" else out
 
 
