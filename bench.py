@@ -150,22 +150,21 @@ def cpu_baseline(rep, emb, S, pipe, cfg):
     sig_s = omh.signatures_c(rep.seqs[rows], rep.lens[rows], cfg.M, synth.HASH_SEED)
     t_mh = (time.perf_counter() - t) * n / ns
     t = time.perf_counter()
-    olsh.candidates_grouped(sig_s, cfg.b, cfg.r)
+    cand_s = olsh.candidates_grouped(sig_s, cfg.b, cfg.r)
     t_lsh = (time.perf_counter() - t) * n / ns
-    P = pipe.P
-    pairs = pipe.pairs[:P].cpu().numpy()
-    Ps = min(P, 300_000)
-    sel = synth.sample_rows(P, Ps, 3)
-    ps = pairs[sel]
+    # the alignment and gate samples are the oracle's own candidates on that subset
+    Ps = min(cand_s.shape[0], 300_000)
+    ps = cand_s[synth.sample_rows(cand_s.shape[0], Ps, 3)].astype(np.int32)
     cells_s = int((rep.lens[ps[:, 0]].astype(np.int64) * rep.lens[ps[:, 1]]).sum())
     t = time.perf_counter()
     al = osw.scores_pairs_parallel(rep.seqs, rep.lens, ps, S, cfg.gap_open, cfg.gap_extend, procs=cores)
     t_sw_s = time.perf_counter() - t
-    cells = pipe.cells()
+    P = pipe.P
+    cells = pipe.cells()  # size of the full workload, used only to scale the sample time
     t_sw = t_sw_s * cells / max(cells_s, 1)
     self_s = osw.self_scores(rep.seqs, rep.lens, S)
     W1, b1, w2, b2 = synth.gate_params(64)
-    Pg = min(P, 100_000)
+    Pg = min(Ps, 100_000)
     pg = ps[:Pg]
     gf = synth.upstream_grad(Pg)
     t = time.perf_counter()
@@ -173,9 +172,10 @@ def cpu_baseline(rep, emb, S, pipe, cfg):
     t_gate = (time.perf_counter() - t) * P / Pg
     total = t_mh + t_lsh + t_sw + t_gate
     return dict(value=cells / total / 1e9, unit="GCUPS", cores=cores, kind="oracle",
-                sample=f"MinHash (C) and LSH (numpy) on the first {ns} sequences, Smith-Waterman (C, "
-                       f"{cores} processes) on {Ps} sampled candidate pairs, gate fwd+bwd (numpy fp64) on "
-                       f"{Pg} pairs; each stage scaled linearly to the full workload",
+                sample=f"MinHash (C) and LSH (numpy) on the first {ns} sequences; Smith-Waterman (C, "
+                       f"{cores} processes) on {Ps} of the oracle's candidate pairs of that subset, gate "
+                       f"fwd+bwd (numpy fp64) on {Pg} of them; each stage's time scaled linearly to the full "
+                       f"workload (sequences, DP cells, pairs)",
                 stage_s=dict(minhash=t_mh, lsh=t_lsh, align=t_sw, gate=t_gate),
                 sw_gcups=cells / t_sw / 1e9)
 
