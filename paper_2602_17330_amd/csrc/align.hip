@@ -24,7 +24,7 @@
 
 namespace subquad {
 
-constexpr int kAlignThreads = 256;
+constexpr int kAlignThreads = 512;
 constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..64)
 constexpr int kMaskCode = 20;          // rows past the shorter sequence's end
 constexpr int kMaskScore = -4096;
@@ -32,6 +32,14 @@ constexpr int kCodes = 21;
 constexpr int kS2Words = 20 * kCodes * kCodes;
 
 __device__ __forceinline__ int max3i(int a, int b, int c) { return max(max(a, b), c); }
+
+// One v_max3_i32 (the compiler otherwise splits a max whose operands it knows to be
+// non-negative into a signed and an unsigned max).
+__device__ __forceinline__ int max3_asm(int a, int b, int c) {
+    int r;
+    asm("v_max3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
 
 __device__ __forceinline__ void pair_lengths(const int32_t *__restrict__ pairs, const int32_t *__restrict__ lens,
                                              int64_t p, int &lmin, int &lmax) {
@@ -136,20 +144,22 @@ __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la,
                     uint32_t w = col[idx2[k]];
                     int s0 = (int)(int16_t)(w & 0xFFFFu);
                     int s1 = (int)w >> 16;
+                    int hh[2];
 #pragma unroll
                     for (int h2 = 0; h2 < 2; ++h2) {
                         const int x = 2 * k + h2;
                         const int s = h2 ? s1 : s0;
                         int e = max3i(E[x] - ge, HG[x], 0);
                         f = max3i(f - ge, hup_go, 0);
-                        int h = max3i(diag + s, e, f);
+                        int h = max3_asm(diag + s, e, f);
                         diag = Hp[x];
                         Hp[x] = h;
                         E[x] = e;
                         HG[x] = h - go;
                         hup_go = HG[x];
-                        best = max(best, h);
+                        hh[h2] = h;
                     }
+                    best = max3_asm(best, hh[0], hh[1]);
                 }
             }
         }
@@ -157,14 +167,27 @@ __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la,
     return best;
 }
 
-template <int MAXROWS>
+// Pairs of one rows bucket (shorter length in (ROWS-8, ROWS]), taken from the length-sorted
+// permutation: the bucket's range is read from the sort's end offsets on the device, so
+// the launch needs no host synchronisation.  Without a permutation (no workspace) every
+// pair is processed in input order with ROWS = the longest allowed row count.
+template <int ROWS>
 __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__restrict__ seqs,
                                                               const int32_t *__restrict__ lens, int64_t n,
-                                                              int32_t stride,
-                                                              const int32_t *__restrict__ pairs, int64_t P,
-                                                              const uint32_t *__restrict__ perm,
+                                                              int32_t stride, const int32_t *__restrict__ pairs,
+                                                              int64_t P, const uint32_t *__restrict__ perm,
+                                                              const uint32_t *__restrict__ bin_end,
                                                               const int8_t *__restrict__ subst, int go, int ge,
                                                               int32_t *__restrict__ scores) {
+    int64_t lo = 0, hi = P;
+    if (perm) {
+        constexpr int g = ROWS / 8;  // 1..8
+        lo = g > 1 ? (int64_t)bin_end[(g - 1) * 64 - 1] : 0;
+        hi = (int64_t)bin_end[g * 64 - 1];
+        if (hi > P) hi = P;
+    }
+    if (lo >= hi) return;  // whole grid
+    if ((int64_t)blockIdx.x * (kAlignThreads / 64) >= ceil_div(hi - lo, 64)) return;  // whole block
     __shared__ uint32_t S2[kS2Words];
     for (int e = threadIdx.x; e < kS2Words; e += blockDim.x) {
         int c = e / (kCodes * kCodes);
@@ -176,53 +199,29 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t nwaves_total = ceil_div(P, 64);
+    const int64_t nw = ceil_div(hi - lo, 64);
     const int64_t wave0 = (int64_t)blockIdx.x * (kAlignThreads / 64) + (threadIdx.x >> 6);
     const int64_t wstep = (int64_t)gridDim.x * (kAlignThreads / 64);
-    for (int64_t wv = wave0; wv < nwaves_total; wv += wstep) {
-        const int64_t idx = wv * 64 + lane;
-        bool valid = idx < P;
+    for (int64_t wv = wave0; wv < nw; wv += wstep) {
+        const int64_t idx = lo + wv * 64 + lane;
+        bool valid = idx < hi;
         int64_t p = 0;
-        int la = 0, lb = 0;
-        const uint8_t *arow = seqs, *brow = seqs;
-        bool bad = false;
         if (valid) {
             p = perm ? (int64_t)perm[idx] : idx;
             valid = p < P;
         }
         if (valid && !pair_ok(pairs, n, p)) {
-            bad = true;
             valid = false;
             scores[p] = -1;
         }
-        (void)bad;
         if (valid) {
             int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
             int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
+            const uint8_t *arow, *brow;
+            int la, lb;
             if (li <= lj) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
             else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
-        }
-        // the wave's unroll: the largest rows bucket among its lanes (sorted input keeps it tight)
-        int rb = valid ? (max(la, 1) + 7) >> 3 : 1;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) rb = max(rb, __shfl_xor(rb, off, 64));
-        rb = __builtin_amdgcn_readfirstlane(rb);
-        int best = 0;
-        if (valid) {
-            la = min(la, MAXROWS);
-            switch (rb) {
-                case 1: best = sw_lane<8>(arow, la, brow, lb, S2, go, ge); break;
-                case 2: best = sw_lane<16>(arow, la, brow, lb, S2, go, ge); break;
-                case 3: best = sw_lane<24>(arow, la, brow, lb, S2, go, ge); break;
-                case 4: best = sw_lane<32>(arow, la, brow, lb, S2, go, ge); break;
-                default:
-                    if constexpr (MAXROWS > 32) {
-                        if (rb <= 6) best = sw_lane<48>(arow, la, brow, lb, S2, go, ge);
-                        else best = sw_lane<64>(arow, la, brow, lb, S2, go, ge);
-                    }
-                    break;
-            }
-            scores[p] = best;
+            scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge);
         }
     }
 }
@@ -282,12 +281,13 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     SQ_LAUNCHED("align_scatter_kernel");
     const int64_t waves = ceil_div(P, 64);
     const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64), (int64_t)device_cus() * 8);
-    if (stride <= 32)
-        align_kernel<32><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, subst, go,
-                                                                       ge, scores);
-    else
-        align_kernel<64><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, subst, go,
-                                                                       ge, scores);
+    const uint32_t *bin_end = hist;  // after the scatter, hist[k] is the end of bin k
+#define SQ_ROWS(R) \
+    align_kernel<R><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, subst, \
+                                                                 go, ge, scores);
+    SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
+    if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
+#undef SQ_ROWS
     SQ_LAUNCHED("align_kernel");
     return SUBQUAD_OK;
 }

@@ -7,10 +7,10 @@
 // distinct 3-mers; taking the minimum over every 3-mer position gives the same value.
 //
 // Mapping to CDNA4: one wave per sequence, lane l owns hash functions l + 64 j (j < J).
-// Every block regenerates the 60*M table words into LDS, laid out [pos][residue][lane][j]
-// so that a lookup with a wave-uniform residue reads consecutive 8*J-byte words (no bank
-// conflicts, one ds_read_b64/b128 per lookup).  The sequence row is wave-uniform and comes
-// through scalar loads.  Stores are 512-byte coalesced rows of sig.
+// Every block regenerates the 60*M table words into LDS as separate hi and lo 32-bit
+// planes, laid out [pos][residue][lane][j], so that a lookup with a wave-uniform residue
+// reads consecutive 4*J-byte words (no bank conflicts).  The sequence row is wave-uniform
+// and comes through scalar loads.  Stores are 512-byte coalesced rows of sig.
 #include "common.h"
 
 namespace subquad {
@@ -26,12 +26,27 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t q) {
 
 constexpr int kMinhashBlock = 512;
 
+// Median of three unsigned words (one VALU instruction).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// The signature word is compared as (hi, lo) 32-bit halves.  The streaming pass reads only
+// the hi halves of the tables and keeps, per hash function, the smallest hi value m1, the
+// second smallest m2 (v_med3 of m1, m2 and the new value) and the position of m1.  When
+// m1 != m2 the minimum hash is unique in its hi half, so its lo half is the lo half at that
+// position, read once at the end.  When m1 == m2 (a repeated 3-mer, or two 3-mers whose
+// hashes share the hi half) that lane redoes the sequence with full 64-bit words.
 template <int J>
 __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const uint8_t *__restrict__ seqs, const int32_t *__restrict__ lens, int64_t n, int32_t stride,
     int32_t M, uint64_t seed, uint64_t *__restrict__ sig) {
-    extern __shared__ uint64_t T[];  // [3][20][64][J]
-    constexpr int kEntries = 3 * 20 * 64 * J;
+    extern __shared__ uint32_t lds[];
+    constexpr int kEntries = 3 * 20 * 64 * J;  // [pos][residue][lane][j]
+    uint32_t *Thi = lds;
+    uint32_t *Tlo = lds + kEntries;
     for (int e = threadIdx.x; e < kEntries; e += blockDim.x) {
         int j = e % J;
         int l = (e / J) % 64;
@@ -42,7 +57,8 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
             int pos = pr / 20, res = pr % 20;
             v = splitmix64_at(seed, ((uint64_t)t * 3 + pos) * 20 + res);
         }
-        T[e] = v;
+        Thi[e] = (uint32_t)(v >> 32);
+        Tlo[e] = (uint32_t)v;
     }
     __syncthreads();
 
@@ -50,45 +66,79 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) +
                          (int64_t)blockIdx.x * (blockDim.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t *Tl = T + lane * J;
     constexpr int kRole = 20 * 64 * J;  // words between position tables
+    const uint32_t *Hl = Thi + lane * J;
+    const uint32_t *Ll = Tlo + lane * J;
 
     for (int64_t i = wave; i < n; i += nwaves) {
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(seqs + i * (int64_t)stride);
+        const uint8_t *row8 = seqs + i * (int64_t)stride;
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(row8);
         const int L = __builtin_amdgcn_readfirstlane(lens[i]);
         const int words = stride >> 2;
-        uint64_t mn[J], x01[J], r0p[J];
+        const int nsh = L - 2;  // shingles
+        uint32_t m1[J], m2[J], arg[J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) { mn[j] = ~0ull; x01[j] = 0; r0p[j] = 0; }
-        int p = 0;
+        for (int j = 0; j < J; ++j) {
+            m1[j] = ~0u;
+            m2[j] = ~0u;
+            arg[j] = 0;
+        }
+        // Four shingles per iteration: residues q .. q+5 come from two row words, and all
+        // twelve lookups are issued before any is used.
 #pragma unroll 1
-        for (int w = 0; w < words && p < L; ++w) {
-            uint32_t word = __builtin_amdgcn_readfirstlane(row[w]);
+        for (int q = 0; q < nsh; q += 4) {
+            const int w = q >> 2;
+            const uint32_t w0 = __builtin_amdgcn_readfirstlane(row[w]);
+            const uint32_t w1 = w + 1 < words ? __builtin_amdgcn_readfirstlane(row[w + 1]) : 0u;
+            uint32_t off[6];
 #pragma unroll
-            for (int k = 0; k < 4; ++k, ++p) {
-                if (p >= L) break;
-                uint32_t c = (word >> (8 * k)) & 0xFFu;
-                c = c < 20u ? c : 19u;
-                const uint64_t *base = Tl + c * (64 * J);
+            for (int k = 0; k < 6; ++k) {
+                uint32_t c = k < 4 ? (w0 >> (8 * k)) & 0xFFu : (w1 >> (8 * (k - 4))) & 0xFFu;
+                off[k] = (c < 20u ? c : 19u) * (64 * J);
+            }
+            uint32_t h[4][J];
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    uint64_t r0 = base[j];
-                    uint64_t r1 = base[kRole + j];
-                    uint64_t r2 = base[2 * kRole + j];
-                    if (p >= 2) {
-                        uint64_t h = x01[j] ^ r2;  // shingle starting at p - 2
-                        mn[j] = h < mn[j] ? h : mn[j];
+            for (int sh = 0; sh < 4; ++sh) {
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    h[sh][j] = Hl[off[sh] + j] ^ Hl[kRole + off[sh + 1] + j] ^ Hl[2 * kRole + off[sh + 2] + j];
+            }
+            const int live = min(4, nsh - q);  // wave-uniform
+#pragma unroll
+            for (int sh = 0; sh < 4; ++sh) {
+                if (sh < live) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const uint32_t v = h[sh][j];
+                        arg[j] = v < m1[j] ? (uint32_t)(q + sh) : arg[j];
+                        m2[j] = umed3(m1[j], m2[j], v);
+                        m1[j] = min(m1[j], v);
                     }
-                    x01[j] = r0p[j] ^ r1;  // R0[p-1] ^ R1[p], shingle starting at p - 1
-                    r0p[j] = r0;
                 }
             }
         }
         uint64_t *out = sig + i * (int64_t)M;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            int t = lane + 64 * j;
-            if (t < M) out[t] = mn[j];
+            const int t = lane + 64 * j;
+            // lo half of the winning shingle (per-lane position; the row is in cache)
+            const uint32_t a0 = min((uint32_t)row8[arg[j]], 19u);
+            const uint32_t a1 = min((uint32_t)row8[arg[j] + 1], 19u);
+            const uint32_t a2 = min((uint32_t)row8[arg[j] + 2], 19u);
+            uint32_t lo = Ll[a0 * (64 * J) + j] ^ Ll[kRole + a1 * (64 * J) + j] ^ Ll[2 * kRole + a2 * (64 * J) + j];
+            uint64_t best = ((uint64_t)m1[j] << 32) | lo;
+            if (m1[j] == m2[j]) {  // rare: exact 64-bit minimum over every position
+                best = ~0ull;
+                for (int q = 0; q + 3 <= L; ++q) {
+                    const uint32_t b0 = min((uint32_t)row8[q], 19u);
+                    const uint32_t b1 = min((uint32_t)row8[q + 1], 19u);
+                    const uint32_t b2 = min((uint32_t)row8[q + 2], 19u);
+                    const int o0 = b0 * (64 * J) + j, o1 = kRole + b1 * (64 * J) + j, o2 = 2 * kRole + b2 * (64 * J) + j;
+                    uint64_t h = ((uint64_t)(Hl[o0] ^ Hl[o1] ^ Hl[o2]) << 32) | (Ll[o0] ^ Ll[o1] ^ Ll[o2]);
+                    best = h < best ? h : best;
+                }
+            }
+            if (t < M) out[t] = best;
         }
     }
 }
@@ -96,7 +146,7 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
 template <int J>
 static int launch_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, int32_t M,
                           uint64_t seed, uint64_t *sig, hipStream_t st) {
-    const size_t lds = sizeof(uint64_t) * 3 * 20 * 64 * J;
+    const size_t lds = 2 * sizeof(uint32_t) * 3 * 20 * 64 * J;
     static bool attr_set = false;
     if (!attr_set) {
         SQ_HIP(hipFuncSetAttribute((const void *)minhash3_kernel<J>,

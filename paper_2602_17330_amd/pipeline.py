@@ -118,6 +118,51 @@ class Pipeline:
         if self.P:
             api.gate_bwd(*self.gate_args(), self.grad_fused, grads=tuple(self.grads), ws=self.gate_ws)
 
+    def lsh_async(self):
+        """Graph-capturable candidate stage: no host synchronisation; the pair sort is sized
+        for the current capacity and the count/status land in device memory."""
+        if not hasattr(self, "dev_count"):
+            self.dev_count = torch.zeros(1, dtype=torch.int64, device=self.device)
+            self.dev_status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        check(lib().subquad_lsh_candidates_async(
+            self.sig.data_ptr(), self.n, self.cfg.M, self.cfg.b, self.cfg.r,
+            None if self.offs is None else self.offs.data_ptr(), self.R, self.lsh_ws.data_ptr(),
+            self.lsh_ws_bytes, self.pairs.data_ptr(), self.rows.data_ptr(), self.cap,
+            self.dev_count.data_ptr(), self.dev_status.data_ptr(), api._stream()))
+
+    def capture(self):
+        """Capture one whole step in a HIP graph (after an eager step has fixed P).
+
+        The candidate stage runs in its asynchronous form with the capacity shrunk to the
+        known P; later stages use that P.  Replaying on the same inputs reproduces the eager
+        step; ``graph_status()`` reports a capacity overflow if the inputs changed."""
+        if self.P == 0:
+            self.step()
+        P = self.P
+        if self.cap != P:
+            self._alloc_pairs(max(P, 1))
+            self.P = P
+        self.lsh_async()          # warm the asynchronous path once outside the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.minhash()
+            self.lsh_async()
+            self.self_scores()
+            self.align()
+            self.gate_fwd()
+            self.loss_grad()
+            self.gate_bwd()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def graph_status(self) -> tuple[int, int]:
+        """(device count of candidate pairs, status) of the last asynchronous candidate stage."""
+        return int(self.dev_count.item()), int(self.dev_status.item())
+
     def step(self, events=None):
         """One pass of the whole hot path. ``events``: list of 7 CUDA events or None."""
         for k, fn in enumerate((self.minhash, self.lsh, self.self_scores, self.align, self.gate_fwd,
