@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rep1m", choices=["rep1m", "zipf100k", "small5k"])
+    ap.add_argument("--workload", default="rep1m", choices=["rep1m", "zipf100k", "small5k", "batch64"])
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="batch64 only: shrink every repertoire (1.0 = 24.03 M sequences)")
+    ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -180,6 +183,70 @@ def cpu_baseline(rep, emb, S, pipe, cfg):
                 sw_gcups=cells / t_sw / 1e9)
 
 
+def bench_batch64(a, torch, sq):
+    """64 repertoires of uneven size: one launch per stage over the whole batch (eager, and
+    as a replayed HIP graph) against 64 separate per-repertoire launch sequences."""
+    import synth
+    from paper_2602_17330_amd import autotune
+    from paper_2602_17330_amd.batching import bytes_per_sequence, plan_batches
+    from paper_2602_17330_amd.pipeline import PathConfig, Pipeline
+    t = time.perf_counter()
+    rep = synth.batch64(scale=a.batch_scale)
+    log(f"generated {rep.n} sequences in {time.perf_counter() - t:.1f} s")
+    emb = synth.embeddings(rep.seqs, rep.lens, 128, device="cuda")
+    S = synth.load_blosum62()
+    W = synth.gate_params(64)
+    cfg = PathConfig(M=128, b=32, r=4)
+    offs = rep.rep_offsets
+    sizes = np.diff(offs)
+    free, total = torch.cuda.mem_get_info()
+    plan = plan_batches(sizes, bytes_per_sequence(128, 32, 128, rep.stride, 40.0), free)
+    log(f"batch plan against {free / 2**30:.0f} GiB free: {len(plan)} batch(es)")
+
+    # (i) 64 separate per-repertoire launch sequences
+    per = []
+    for k in range(len(sizes)):
+        lo, hi = int(offs[k]), int(offs[k + 1])
+        per.append(Pipeline(rep.seqs[lo:hi], rep.lens[lo:hi], rep.vgene[lo:hi], rep.family[lo:hi], emb[lo:hi],
+                            S, *W, cfg=cfg))
+    for pp in per:
+        pp.step()
+    torch.cuda.synchronize()
+    P_per = sum(pp.P for pp in per)
+    cells = sum(pp.cells() for pp in per)
+
+    def run_per():
+        for pp in per:
+            pp.step()
+
+    t_per = time_region(torch, run_per, a.steps, a.warmup)
+    del per
+    torch.cuda.empty_cache()
+
+    # (ii) one launch per stage over all repertoires
+    big = Pipeline(rep.seqs, rep.lens, rep.vgene, rep.family, emb, S, *W, cfg=cfg, rep_offsets=offs)
+    big.step()
+    torch.cuda.synchronize()
+    assert big.P == P_per, (big.P, P_per)
+    tuned = autotune.tune(big) if a.tune else None
+    t_big = time_region(torch, big.step, a.steps, a.warmup)
+    big.capture()
+    t_graph = time_region(torch, big.replay, a.steps, a.warmup)
+    out = {
+        "metric": "batched vs per-repertoire hot path (64 repertoires)",
+        "value": cells / t_graph / 1e9, "unit": "GCUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": t_graph * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"batch64: 64 repertoires, {rep.n} sequences (log-uniform 1e4..2e6 x "
+                               f"{a.batch_scale}), lengths 8-30, M=128, 32x4, d=128, H=64",
+                   "candidates": int(P_per), "cells": int(cells), "batches": len(plan)},
+        "per_repertoire_ms": t_per * 1e3, "batched_eager_ms": t_big * 1e3, "batched_graph_ms": t_graph * 1e3,
+        "speedup_graph_vs_per_repertoire": t_per / t_graph, "speedup_eager_vs_per_repertoire": t_per / t_big,
+        "autotune": tuned,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -192,6 +259,8 @@ def main():
     import synth
 
     sq.lib()  # fails loudly if the library is missing
+    if a.workload == "batch64":
+        return bench_batch64(a, torch, sq)
     log(f"building workload {a.workload}")
     rep, emb = build_workload(a.workload)
     S = synth.load_blosum62()
@@ -206,6 +275,11 @@ def main():
     P = pipe.P
     cells = pipe.cells()
     log(f"P={P} cells={cells}")
+    tuned = None
+    if a.tune:
+        from paper_2602_17330_amd import autotune
+        tuned = autotune.tune(pipe)
+        log(f"autotuned: {tuned['best']}")
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
     stage_ms = np.zeros(len(STAGES))
@@ -283,6 +357,7 @@ def main():
         "roofline": roof,
         "rooflines": rooflines,
         "cpu_baseline": cpu,
+        "autotune": tuned,
     }
     print(json.dumps(out), flush=True)
 

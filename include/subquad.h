@@ -54,6 +54,20 @@ const char *subquad_last_error(void);
 const char *subquad_version(void);
 
 /*
+ * Launch-shape knobs (process-wide, every GPU).  They choose grid and block shapes only and
+ * never change any result; an autotuner may set them.  Values <= 0 restore the default.
+ */
+enum subquad_knob {
+    SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU = 0,  /* persistent MinHash blocks per CU (default 2) */
+    SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU = 1,    /* persistent alignment blocks per CU (default 8) */
+    SUBQUAD_KNOB_GATE_GROUPS_PER_CU = 2,     /* 16-lane pair groups per CU (default 64)       */
+    SUBQUAD_KNOB_EMIT_THREADS = 3,           /* LSH run-scan block size (default 256)          */
+    SUBQUAD_KNOB_COUNT = 4
+};
+int subquad_set_knob(int32_t knob, int32_t value);  /* SUBQUAD_ERR_ARG for an unknown knob */
+int32_t subquad_get_knob(int32_t knob);             /* current value, -1 if unknown        */
+
+/*
  * subquad_check_seqs -- validate a sequence batch (Algorithm 1, preprocessing: the padded
  * sequence rows every later stage reads).
  *   seqs [n][stride] u8, lens [n] i32: the batch.  k: shingle length (1..5).

@@ -18,6 +18,8 @@ c_i32, c_i64, c_u64, c_sz, c_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
 SIGNATURES = {
     "subquad_last_error": (ctypes.c_char_p, []),
     "subquad_version": (ctypes.c_char_p, []),
+    "subquad_set_knob": (ctypes.c_int, [c_i32, c_i32]),
+    "subquad_get_knob": (c_i32, [c_i32]),
     "subquad_check_seqs": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_p, c_p]),
     "subquad_minhash": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_i32, c_u64, c_p, c_p]),
     "subquad_lsh_workspace_bytes": (c_sz, [c_i64, c_i32, c_i64]),
@@ -37,6 +39,10 @@ SIGNATURES = {
     "subquad_gate_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
 }
+
+
+KNOBS = {"minhash_blocks_per_cu": 0, "align_blocks_per_cu": 1, "gate_groups_per_cu": 2,
+         "emit_threads": 3}
 
 
 class SubquadError(RuntimeError):

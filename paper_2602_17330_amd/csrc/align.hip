@@ -280,7 +280,8 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     align_scatter_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, hist, perm);
     SQ_LAUNCHED("align_scatter_kernel");
     const int64_t waves = ceil_div(P, 64);
-    const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64), (int64_t)device_cus() * 8);
+    const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64),
+                                              (int64_t)device_cus() * knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU));
     const uint32_t *bin_end = hist;  // after the scatter, hist[k] is the end of bin k
 #define SQ_ROWS(R) \
     align_kernel<R><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, subst, \

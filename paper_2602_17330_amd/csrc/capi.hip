@@ -1,4 +1,5 @@
 // Library-wide entry points: error reporting, version, sequence validation.
+#include <atomic>
 #include <cstdarg>
 #include <mutex>
 #include <vector>
@@ -56,6 +57,14 @@ __global__ void check_seqs_kernel(const uint8_t *__restrict__ seqs, const int32_
     }
 }
 
+static std::atomic<int> g_knobs[SUBQUAD_KNOB_COUNT] = {};
+static const int kKnobDefault[SUBQUAD_KNOB_COUNT] = {2, 8, 64, 256};
+
+int knob(int which) {
+    int v = g_knobs[which].load(std::memory_order_relaxed);
+    return v > 0 ? v : kKnobDefault[which];
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -68,6 +77,20 @@ using namespace subquad;
 extern "C" const char *subquad_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char *subquad_version(void) { return "subquad 0.1 (gfx950)"; }
+
+extern "C" int subquad_set_knob(int32_t which, int32_t value) {
+    clear_error();
+    SQ_REQUIRE(which >= 0 && which < SUBQUAD_KNOB_COUNT, SUBQUAD_ERR_ARG, "unknown knob %d", which);
+    if (which == SUBQUAD_KNOB_EMIT_THREADS && value > 0)
+        SQ_REQUIRE(value % 64 == 0 && value <= 1024, SUBQUAD_ERR_ARG, "emit threads must be a multiple of 64 <= 1024");
+    g_knobs[which].store(value > 0 ? value : 0, std::memory_order_relaxed);
+    return SUBQUAD_OK;
+}
+
+extern "C" int32_t subquad_get_knob(int32_t which) {
+    if (which < 0 || which >= SUBQUAD_KNOB_COUNT) return -1;
+    return knob(which);
+}
 
 extern "C" int subquad_check_seqs(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
                                   int32_t k, int64_t *n_bad, void *stream) {

@@ -52,6 +52,9 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Number of compute units of the current device (cached per process per device).
 int device_cus();
 
+// Launch-shape knob value (default when unset).
+int knob(int which);
+
 // Upper bound of a repertoire id: the r with rep_offsets[r] <= i < rep_offsets[r+1].
 __device__ __forceinline__ int64_t rep_of(const int64_t *__restrict__ offs, int64_t R, int64_t i) {
     int64_t lo = 0, hi = R;  // answer in [lo, hi)

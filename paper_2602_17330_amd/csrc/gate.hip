@@ -315,7 +315,8 @@ static int gate_validate(const GateIn &in) {
 
 static int64_t gate_blocks(int64_t P) {
     // enough groups to fill the chip, each with a contiguous chunk of pairs
-    int64_t groups = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * 64));
+    int64_t groups = std::max<int64_t>(
+        1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU)));
     return ceil_div(groups, kGateThreads / kGroup);
 }
 

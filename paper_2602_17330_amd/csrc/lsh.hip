@@ -25,7 +25,6 @@ namespace subquad {
 
 constexpr int kKeysTileSeqs = 64;
 constexpr int kKeysThreads = 256;
-constexpr int kEmitThreads = 256;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 33)) * 0xFF51AFD7ED558CCDull;
@@ -72,7 +71,7 @@ __device__ __forceinline__ bool tuple_equal(const uint64_t *__restrict__ sig, in
 }
 
 // Step 3.  One thread per sorted record; the thread walks the rest of its run.
-__global__ __launch_bounds__(kEmitThreads) void lsh_emit_kernel(
+__global__ __launch_bounds__(1024) void lsh_emit_kernel(
     const uint64_t *__restrict__ srec, int64_t total, int64_t n, const uint64_t *__restrict__ sig, int32_t M,
     int32_t b, int32_t r, const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
@@ -212,7 +211,8 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     uint64_t *sorted = nullptr;
     int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted);
     if (rc != SUBQUAD_OK) return rc;
-    lsh_emit_kernel<<<(unsigned)ceil_div(recs, kEmitThreads), kEmitThreads, 0, st>>>(
+    const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
+    lsh_emit_kernel<<<(unsigned)ceil_div(recs, emit_threads), emit_threads, 0, st>>>(
         sorted, recs, n, sig, M, b, r, F, offs, R, nb, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
     SQ_LAUNCHED("lsh_emit_kernel");
     return SUBQUAD_OK;

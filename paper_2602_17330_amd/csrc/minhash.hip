@@ -154,7 +154,7 @@ static int launch_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, i
         attr_set = true;
     }
     const int waves_per_block = kMinhashBlock / kWave;
-    const int per_cu = J <= 2 ? 2 : 1;
+    const int per_cu = J <= 2 ? std::min(knob(SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU), 2) : 1;  // LDS bound
     int64_t blocks = std::min<int64_t>(ceil_div(n, waves_per_block), (int64_t)device_cus() * per_cu);
     minhash3_kernel<J><<<(unsigned)blocks, kMinhashBlock, lds, st>>>(seqs, lens, n, stride, M, seed, sig);
     SQ_LAUNCHED("minhash3_kernel");
