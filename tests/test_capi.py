@@ -108,3 +108,11 @@ def test_binding_rejects_host_tensors():
         sq.minhash(torch.zeros((2, 32), dtype=torch.uint8), torch.full((2,), 5, dtype=torch.int32), 64)
     with pytest.raises(ValueError):
         sq.check_subst([[0] * 20] * 19)
+
+
+def test_knobs(L):
+    assert L.subquad_get_knob(0) == 2 and L.subquad_get_knob(1) == 8
+    assert L.subquad_set_knob(2, 128) == 0 and L.subquad_get_knob(2) == 128
+    assert L.subquad_set_knob(2, 0) == 0 and L.subquad_get_knob(2) == 64
+    assert L.subquad_set_knob(3, 100) == 1            # not a multiple of 64
+    assert L.subquad_set_knob(9, 1) == 1 and L.subquad_get_knob(9) == -1

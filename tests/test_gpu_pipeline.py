@@ -137,3 +137,25 @@ def test_graph_replay_matches_eager():
             assert torch.allclose(a, b, rtol=1e-5, atol=1e-7)
         assert torch.allclose(pipe.grads[4], eager["grads"][4], rtol=1e-4, atol=1e-6)
         del junk
+
+
+def test_knobs_never_change_results():
+    """Launch-shape knobs (the autotuner's search space) leave every result unchanged."""
+    from paper_2602_17330_amd import autotune
+    rep = workload("small5k")
+    S = synth.load_blosum62()
+    emb = synth.embeddings(rep.seqs, rep.lens, 64)
+    W = synth.gate_params(64)
+    say("knob invariance")
+    base = run_gpu(rep, S, emb, W)
+    try:
+        for name, vals in autotune.CANDIDATES.items():
+            for v in vals:
+                autotune.set_knob(name, v)
+                got = run_gpu(rep, S, emb, W)
+                for k in ("sig", "pairs", "rows", "scores"):
+                    assert np.array_equal(got[k], base[k]), (name, v, k)
+                assert np.allclose(got["fused"], base["fused"], rtol=1e-6, atol=1e-7)
+            autotune.set_knob(name, 0)
+    finally:
+        autotune.reset()
