@@ -168,3 +168,31 @@ def test_rep1m_full_size():
     sample = synth.sample_rows(rep.n, 40, 6)
     for i, ref in row_candidates_sampled(sig, sample, 32, 4).items():
         assert np.array_equal(got[rows[i]:rows[i + 1], 1], ref), i
+
+
+def test_edge_cases():
+    rep = synth.tiny(n_families=20, fam_size=5, seed=51)
+    sig = omh.signatures(rep.seqs, rep.lens, 64, synth.HASH_SEED)
+    say("lsh edge cases")
+    # a single sequence: no pairs, offsets all zero
+    got, rows = _gpu(sig[:1], 16, 4)
+    assert got.shape == (0, 2) and np.array_equal(rows, [0, 0])
+    # b*r < M: only the first b*r rows take part
+    got, _ = _gpu(sig, 5, 3)
+    assert np.array_equal(got, olsh.candidates(sig, 5, 3))
+    # empty repertoires inside the offsets
+    offs = [0, 0, 40, 40, 40, 70, rep.n, rep.n]
+    got, _ = _gpu(sig, 16, 4, offs=offs)
+    assert np.array_equal(got, olsh.candidates(sig, 16, 4, rep_offsets=offs))
+
+
+def test_two_thousand_identical():
+    """2,000 identical signatures: about 2 million pairs from one bucket in every band."""
+    rep = synth.tiny(n_families=10, fam_size=5, seed=52)
+    sig = omh.signatures(rep.seqs, rep.lens, 64, synth.HASH_SEED)
+    sig = np.concatenate([sig, np.repeat(sig[3:4], 2000, axis=0)])
+    say("lsh 2000 identical")
+    got, rows = _gpu(sig, 16, 4)
+    ref = olsh.candidates_grouped(sig, 16, 4)
+    assert ref.shape[0] >= 2001 * 2000 // 2
+    assert np.array_equal(got, ref)
