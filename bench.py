@@ -281,18 +281,21 @@ def main():
         tuned = autotune.tune(pipe)
         log(f"autotuned: {tuned['best']}")
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
-    stage_ms = np.zeros(len(STAGES))
+    from paper_2602_17330_amd import _lib
     for _ in range(a.warmup):
         pipe.step()
     torch.cuda.synchronize()
+    # timed region: whole steps, with every main kernel bracketed by HIP events on its stream
+    _lib.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        ev[0].record()
-        pipe.step(events=ev[1:])
+        pipe.step()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / a.steps
-    # event timings come from the last step only plus a separate pass below
+    kern = _lib.profile_report()
+    _lib.profile_enable(False)
+    # per-stage split of a few more steps (events between stages, for the stage table)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(STAGES) + 1)]
     per = np.zeros(len(STAGES))
     reps = max(3, min(a.steps, 10))
     for _ in range(reps):
@@ -302,28 +305,44 @@ def main():
         per += np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(len(STAGES))])
     stage_ms = per / reps
     log(f"step {wall * 1e3:.3f} ms; stages " + ", ".join(f"{s}={m:.3f}" for s, m in zip(STAGES, stage_ms)))
+    log("kernels: " + ", ".join(f"{k}={v[1] / a.steps:.3f}ms/step({v[0] // a.steps}x)" for k, v in kern.items()))
 
     n = rep.n
-    M, b, d = cfg.M, cfg.b, emb.shape[1]
-    bytes_alg = {
-        "minhash": n * (rep.stride + 4) + n * M * 8,
-        "gate_fwd": P * (2 * d * 4 + 8 + 4 + 4),
-        "gate_bwd": P * (2 * d * 4 + 2 * d * 4 + 8 + 4 + 4 + 4),
-        "lsh": n * b * cfg.r * 8 + 8 * P,
+    M, b, r, d = cfg.M, cfg.b, cfg.r, emb.shape[1]
+    recs = n * b
+    # algorithmic bytes (or int32 ops) of ONE launch of each kernel
+    alg = {
+        "minhash3_kernel": ("hbm", n * (rep.stride + 4) + n * M * 8),
+        "lsh_keys_kernel": ("hbm", n * b * r * 8 + recs * 8 + recs),
+        "sort_records_scatter": ("hbm", 2 * recs * 8),
+        "sort_records_hist": ("hbm", recs * 8),
+        "lsh_emit_kernel": ("hbm", recs * 8 + 8 * P),
+        "sort_pairs_scatter": ("hbm", 2 * P * 8),
+        "sort_pairs_hist": ("hbm", P * 8),
+        "gate_fwd_kernel": ("hbm", P * (2 * d * 4 + 16)),
+        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 2 * d * 4 + 20)),
+        "align_kernel": ("alu", cells * SW_OPS_PER_CELL),
     }
-    sidx = {s: k for k, s in enumerate(STAGES)}
-    rooflines = {}
-    for s, by in bytes_alg.items():
-        t = stage_ms[sidx[s]] / 1e3
-        ach = by / t / 1e9
-        rooflines[s] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                            alg_bytes=by, ms=stage_ms[sidx[s]])
-    t_al = stage_ms[sidx["align"]] / 1e3
-    ops = cells * SW_OPS_PER_CELL / t_al / 1e12
-    rooflines["align"] = dict(bound="alu", achieved=ops, peak=ALU_PEAK_TOPS, unit="Tops/s", frac=ops / ALU_PEAK_TOPS,
-                              gcups=cells / t_al / 1e9, ms=stage_ms[sidx["align"]])
-    dominant = max(rooflines, key=lambda s: rooflines[s]["ms"])
-    roof = dict(rooflines[dominant], kernel=dominant, traffic=None)
+    kernels = {}
+    for name, (launches, total_ms) in kern.items():
+        avg_ms = total_ms / max(launches, 1)
+        entry = {"launches_per_step": launches / a.steps, "avg_launch_ms": avg_ms, "ms_per_step": total_ms / a.steps}
+        if name in alg:
+            bound, work = alg[name]
+            if bound == "hbm":
+                ach = work / (avg_ms / 1e3) / 1e9
+                entry.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                             alg_bytes_per_launch=work)
+            else:
+                ach = work / (avg_ms / 1e3) / 1e12
+                entry.update(bound="alu", achieved=ach, peak=ALU_PEAK_TOPS, unit="Tops/s", frac=ach / ALU_PEAK_TOPS,
+                             alg_ops_per_launch=work, gcups=cells / (avg_ms / 1e3) / 1e9)
+        kernels[name] = entry
+    dominant = max((k for k in kernels if "bound" in kernels[k]), key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dominant]
+    roof = {"bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"], "unit": kd["unit"],
+            "frac": kd["frac"], "traffic": None, "kernel": dominant, "avg_launch_ms": kd["avg_launch_ms"]}
+    sw_gcups = kernels.get("align_kernel", {}).get("gcups")
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
     if a.calib_copy:
@@ -351,11 +370,11 @@ def main():
                                f"M={M}, {b}x{cfg.r} bands, BLOSUM62 gaps 10/1, d={d}, H=64; step = MinHash + "
                                f"LSH + Smith-Waterman + gate fwd + loss grad + gate bwd",
                    "n": n, "candidates": P, "cells": cells, "parallelism": "single GPU"},
-        "sw_kernel_gcups": rooflines["align"]["gcups"],
+        "sw_kernel_gcups": sw_gcups,
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
         "gate_2p20": gate,
         "roofline": roof,
-        "rooflines": rooflines,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "autotune": tuned,
     }

@@ -68,6 +68,16 @@ int subquad_set_knob(int32_t knob, int32_t value);  /* SUBQUAD_ERR_ARG for an un
 int32_t subquad_get_knob(int32_t knob);             /* current value, -1 if unknown        */
 
 /*
+ * Per-kernel timing (tracing).  While enabled, every main kernel launch is bracketed by two
+ * HIP events recorded on its own stream.  subquad_profile_report synchronises those events
+ * and writes one line per kernel name, "name launches total_ms\n", into buf (host, len
+ * bytes, always NUL-terminated); it returns the bytes needed (excluding the NUL).
+ * Enabling (on != 0) or disabling clears the records.  Not for use under graph capture.
+ */
+int subquad_profile_enable(int32_t on);
+int64_t subquad_profile_report(char *buf, size_t len);
+
+/*
  * subquad_check_seqs -- validate a sequence batch (Algorithm 1, preprocessing: the padded
  * sequence rows every later stage reads).
  *   seqs [n][stride] u8, lens [n] i32: the batch.  k: shingle length (1..5).

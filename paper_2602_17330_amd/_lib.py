@@ -20,6 +20,8 @@ SIGNATURES = {
     "subquad_version": (ctypes.c_char_p, []),
     "subquad_set_knob": (ctypes.c_int, [c_i32, c_i32]),
     "subquad_get_knob": (c_i32, [c_i32]),
+    "subquad_profile_enable": (ctypes.c_int, [c_i32]),
+    "subquad_profile_report": (c_i64, [ctypes.c_char_p, c_sz]),
     "subquad_check_seqs": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_p, c_p]),
     "subquad_minhash": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_i32, c_u64, c_p, c_p]),
     "subquad_lsh_workspace_bytes": (c_sz, [c_i64, c_i32, c_i64]),
@@ -68,3 +70,19 @@ def lib() -> ctypes.CDLL:
 def check(status: int) -> None:
     if status != OK:
         raise SubquadError(status, lib().subquad_last_error().decode())
+
+
+def profile_enable(on: bool = True) -> None:
+    check(lib().subquad_profile_enable(1 if on else 0))
+
+
+def profile_report() -> dict:
+    """{kernel name: (launches, total ms)} of the launches timed since profile_enable."""
+    need = lib().subquad_profile_report(None, 0)
+    buf = ctypes.create_string_buffer(int(need) + 1)
+    lib().subquad_profile_report(buf, len(buf))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -283,12 +283,15 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64),
                                               (int64_t)device_cus() * knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU));
     const uint32_t *bin_end = hist;  // after the scatter, hist[k] is the end of bin k
-#define SQ_ROWS(R) \
+    {
+        ProfScope prof("align_kernel", st);
+#define SQ_ROWS(R)                                                                                                   \
     align_kernel<R><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, subst, \
                                                                  go, ge, scores);
-    SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
-    if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
+        SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
+        if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
 #undef SQ_ROWS
+    }
     SQ_LAUNCHED("align_kernel");
     return SUBQUAD_OK;
 }

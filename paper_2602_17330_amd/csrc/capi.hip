@@ -1,6 +1,7 @@
 // Library-wide entry points: error reporting, version, sequence validation.
 #include <atomic>
 #include <cstdarg>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -65,6 +66,57 @@ int knob(int which) {
     return v > 0 ? v : kKnobDefault[which];
 }
 
+struct ProfRec {
+    std::string name;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+static std::mutex g_prof_mu;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_prof_pool;  // events are reused, so timing adds no creation cost
+static std::atomic<bool> g_prof_on{false};
+
+static void prof_clear_locked() {
+    for (auto &r : g_prof) {
+        if (r.a) g_prof_pool.push_back(r.a);
+        if (r.b) g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+}
+
+static hipEvent_t prof_event_locked() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int prof_begin(hipStream_t st) {
+    if (!g_prof_on.load(std::memory_order_relaxed)) return -1;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r;
+    r.a = prof_event_locked();
+    r.b = prof_event_locked();
+    if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {
+        if (r.a) g_prof_pool.push_back(r.a);
+        if (r.b) g_prof_pool.push_back(r.b);
+        return -1;
+    }
+    g_prof.push_back(r);
+    return (int)g_prof.size() - 1;
+}
+
+void prof_end(int token, const char *name, hipStream_t st) {
+    if (token < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (token >= (int)g_prof.size()) return;
+    g_prof[token].name = name;
+    (void)hipEventRecord(g_prof[token].b, st);
+}
+
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -90,6 +142,40 @@ extern "C" int subquad_set_knob(int32_t which, int32_t value) {
 extern "C" int32_t subquad_get_knob(int32_t which) {
     if (which < 0 || which >= SUBQUAD_KNOB_COUNT) return -1;
     return knob(which);
+}
+
+extern "C" int subquad_profile_enable(int32_t on) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on.store(on != 0);
+    return SUBQUAD_OK;
+}
+
+extern "C" int64_t subquad_profile_report(char *buf, size_t len) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::vector<std::pair<std::string, std::pair<int, double>>> agg;
+    for (auto &r : g_prof) {
+        if (r.name.empty()) continue;
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        bool found = false;
+        for (auto &e : agg)
+            if (e.first == r.name) { e.second.first += 1; e.second.second += ms; found = true; break; }
+        if (!found) agg.push_back({r.name, {1, (double)ms}});
+    }
+    std::string out;
+    char line[256];
+    for (auto &e : agg) {
+        snprintf(line, sizeof(line), "%s %d %.6f\n", e.first.c_str(), e.second.first, e.second.second);
+        out += line;
+    }
+    if (buf && len) {
+        size_t k = std::min(len - 1, out.size());
+        memcpy(buf, out.data(), k);
+        buf[k] = 0;
+    }
+    return (int64_t)out.size();
 }
 
 extern "C" int subquad_check_seqs(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,

@@ -55,6 +55,19 @@ int device_cus();
 // Launch-shape knob value (default when unset).
 int knob(int which);
 
+// Opt-in per-kernel event timing: prof_begin returns a token (or -1 when disabled) and
+// prof_end records the closing event for it.
+int prof_begin(hipStream_t st);
+void prof_end(int token, const char *name, hipStream_t st);
+
+struct ProfScope {
+    int tok;
+    const char *name;
+    hipStream_t st;
+    ProfScope(const char *n, hipStream_t s) : tok(prof_begin(s)), name(n), st(s) {}
+    ~ProfScope() { prof_end(tok, name, st); }
+};
+
 // Upper bound of a repertoire id: the r with rep_offsets[r] <= i < rep_offsets[r+1].
 __device__ __forceinline__ int64_t rep_of(const int64_t *__restrict__ offs, int64_t R, int64_t i) {
     int64_t lo = 0, hi = R;  // answer in [lo, hi)

@@ -323,6 +323,7 @@ static int64_t gate_blocks(int64_t P) {
 template <int NV>
 static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t st) {
     const int64_t blocks = gate_blocks(in.P);
+    ProfScope prof("gate_fwd_kernel", st);
     switch (in.H / kGroup) {
 #define SQ_CASE(U) \
     case U: gate_fwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, fused, gate); break;
@@ -339,6 +340,7 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
 template <int NV>
 static int gate_bwd_nv(const GateIn &in, const float *gf, float *demb, double *wacc, hipStream_t st) {
     const int64_t blocks = gate_blocks(in.P);
+    ProfScope prof("gate_bwd_kernel", st);
     switch (in.H / kGroup) {
 #define SQ_CASE(U) \
     case U: gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, demb, wacc); break;

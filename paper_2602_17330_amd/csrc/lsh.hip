@@ -205,15 +205,21 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     SQ_LAUNCHED("lsh_init_kernel");
     const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;
     SQ_REQUIRE(lds <= 64 * 1024, SUBQUAD_ERR_ARG, "too many bands");
-    lsh_keys_kernel<<<(unsigned)ceil_div(n, kKeysTileSeqs), kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, rec_a,
-                                                                                      F);
+    {
+        ProfScope prof("lsh_keys_kernel", st);
+        lsh_keys_kernel<<<(unsigned)ceil_div(n, kKeysTileSeqs), kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R,
+                                                                                          rec_a, F);
+    }
     SQ_LAUNCHED("lsh_keys_kernel");
     uint64_t *sorted = nullptr;
-    int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted);
+    int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted, "sort_records");
     if (rc != SUBQUAD_OK) return rc;
     const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
-    lsh_emit_kernel<<<(unsigned)ceil_div(recs, emit_threads), emit_threads, 0, st>>>(
-        sorted, recs, n, sig, M, b, r, F, offs, R, nb, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
+    {
+        ProfScope prof("lsh_emit_kernel", st);
+        lsh_emit_kernel<<<(unsigned)ceil_div(recs, emit_threads), emit_threads, 0, st>>>(
+            sorted, recs, n, sig, M, b, r, F, offs, R, nb, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
+    }
     SQ_LAUNCHED("lsh_emit_kernel");
     return SUBQUAD_OK;
 }
@@ -228,7 +234,8 @@ static int lsh_back(int64_t n, char *ws, const LshLayout &L, int64_t cap, int64_
     uint64_t *sorted = reinterpret_cast<uint64_t *>(ws + L.pk_a);
     if (sort_n > 0) {
         int rc = radix_sort_u64(reinterpret_cast<uint64_t *>(ws + L.pk_a), reinterpret_cast<uint64_t *>(ws + L.pk_b),
-                                sort_n, clamped, 0, 2 * nb, ws + L.radix, L.total - L.radix, st, &sorted);
+                                sort_n, clamped, 0, 2 * nb, ws + L.radix, L.total - L.radix, st, &sorted,
+                                "sort_pairs");
         if (rc != SUBQUAD_OK) return rc;
         int64_t blocks = std::min<int64_t>(ceil_div(sort_n, 256), (int64_t)device_cus() * 16);
         lsh_pairs_kernel<<<(unsigned)blocks, 256, 0, st>>>(sorted, clamped, cap, nb, pairs);

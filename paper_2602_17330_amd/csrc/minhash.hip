@@ -156,6 +156,7 @@ static int launch_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, i
     const int waves_per_block = kMinhashBlock / kWave;
     const int per_cu = J <= 2 ? std::min(knob(SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU), 2) : 1;  // LDS bound
     int64_t blocks = std::min<int64_t>(ceil_div(n, waves_per_block), (int64_t)device_cus() * per_cu);
+    ProfScope prof("minhash3_kernel", st);
     minhash3_kernel<J><<<(unsigned)blocks, kMinhashBlock, lds, st>>>(seqs, lens, n, stride, M, seed, sig);
     SQ_LAUNCHED("minhash3_kernel");
     return SUBQUAD_OK;

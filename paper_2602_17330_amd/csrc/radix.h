@@ -19,7 +19,7 @@ size_t radix_scratch_bytes(int64_t n_cap);
 // device, so the call never synchronises).  *result receives a or b: the sorted buffer.
 int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev, int lo_bit,
                    int key_bits, void *scratch, size_t scratch_bytes, hipStream_t st,
-                   uint64_t **result);
+                   uint64_t **result, const char *tag = "radix");
 
 // In-place exclusive prefix sum of `count` 32-bit values (sum must fit in 32 bits).
 size_t scan_scratch_bytes(int64_t count);

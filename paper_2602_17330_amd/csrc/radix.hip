@@ -214,7 +214,9 @@ size_t radix_scratch_bytes(int64_t n_cap) {
 }
 
 int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev, int lo_bit, int key_bits,
-                   void *scratch, size_t scratch_bytes, hipStream_t st, uint64_t **result) {
+                   void *scratch, size_t scratch_bytes, hipStream_t st, uint64_t **result, const char *tag) {
+    const std::string hist_name = std::string(tag) + "_hist", scan_name = std::string(tag) + "_scan",
+                      scatter_name = std::string(tag) + "_scatter";
     *result = a;
     if (n_cap <= 1 || key_bits <= 0) return SUBQUAD_OK;
     SQ_REQUIRE(scratch_bytes >= radix_scratch_bytes(n_cap), SUBQUAD_ERR_WORKSPACE, "radix scratch too small");
@@ -228,12 +230,23 @@ int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev
         const int bits = std::min(kRadixBits, key_bits - done);
         const int shift = lo_bit + done;
         const uint32_t dmask = (1u << bits) - 1u;
-        radix_hist_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask, hist, nblocks);
+        {
+            ProfScope prof(hist_name.c_str(), st);
+            radix_hist_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask, hist,
+                                                                           nblocks);
+        }
         SQ_LAUNCHED("radix_hist_kernel");
-        int rc = scan_exclusive_u32(hist, hist_n, scan_scratch, st);
+        int rc;
+        {
+            ProfScope prof(scan_name.c_str(), st);
+            rc = scan_exclusive_u32(hist, hist_n, scan_scratch, st);
+        }
         if (rc != SUBQUAD_OK) return rc;
-        radix_scatter_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift, dmask, hist,
-                                                                          nblocks);
+        {
+            ProfScope prof(scatter_name.c_str(), st);
+            radix_scatter_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift, dmask,
+                                                                              hist, nblocks);
+        }
         SQ_LAUNCHED("radix_scatter_kernel");
         std::swap(src, dst);
     }
