@@ -217,6 +217,24 @@ int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens
                      float *dW1, float *db1, float *dw2, float *db2, float *demb, void *ws,
                      size_t ws_bytes, void *stream);
 
+/*
+ * subquad_graph_topk -- sparse similarity graph from the fused affinities (Algorithm 1,
+ * graph construction; Sec. 3.7; the evaluation links receptors whose fused similarity
+ * exceeds tau = 0.7, Appendix B sensitivity study).  Every pair (i, j) of `pairs` with
+ * w[p] >= tau gives the directed edges i -> j and j -> i of weight w[p]; each node's edges
+ * are ordered by weight descending, then neighbour id ascending, and the first k are kept
+ * (k = 0: all).  NaN weights never pass.
+ *   pairs [P][2] i32, w [P] f32 (e.g. the output of subquad_gate_fwd), n nodes.
+ *   ws / ws_bytes: at least subquad_graph_workspace_bytes(n, P) bytes, 256-byte aligned.
+ *   row_offsets [n+1] i64, cols [cap] i32, vals [cap] f32 (out): the CSR graph.
+ *   nnz (host out): number of entries.  cap >= 2 * P always suffices.
+ * Synchronises `stream` once.  SUBQUAD_ERR_CAPACITY (with *nnz set) if nnz > cap.
+ */
+size_t subquad_graph_workspace_bytes(int64_t n, int64_t P);
+int subquad_graph_topk(const int32_t *pairs, const float *w, int64_t P, int64_t n, float tau,
+                       int32_t k, void *ws, size_t ws_bytes, int64_t *row_offsets, int32_t *cols,
+                       float *vals, int64_t cap, int64_t *nnz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -218,3 +218,21 @@ class GateFn(torch.autograd.Function):
         dW1, db1, dw2, db2, demb = gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2,
                                             grad_fused.contiguous(), need_emb=ctx.needs_input_grad[0])
         return demb, dW1, db1, dw2, db2, None, None, None, None, None
+
+
+def graph_topk(pairs: torch.Tensor, w: torch.Tensor, n: int, tau: float = 0.7, k: int = 0):
+    """CSR similarity graph: (row_offsets int64[n+1], cols int32[nnz], vals float32[nnz])."""
+    pairs = _dev(pairs, torch.int32, "pairs")
+    w = _dev(w, torch.float32, "w")
+    P = pairs.shape[0]
+    dev = pairs.device
+    need = int(lib().subquad_graph_workspace_bytes(n, P))
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    cap = max(1, 2 * P if k == 0 else min(2 * P, n * k))
+    rows = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    cols = torch.empty(cap, dtype=torch.int32, device=dev)
+    vals = torch.empty(cap, dtype=torch.float32, device=dev)
+    nnz = ctypes.c_int64(0)
+    check(lib().subquad_graph_topk(_ptr(pairs), _ptr(w), P, n, float(tau), int(k), _ptr(ws), need, _ptr(rows),
+                                   _ptr(cols), _ptr(vals), cap, ctypes.byref(nnz), _stream()))
+    return rows, cols[: nnz.value], vals[: nnz.value]
