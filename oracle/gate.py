@@ -60,9 +60,18 @@ def forward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, return_
     return f
 
 
-def backward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, grad_f):
+def relu_ambiguous(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, kappa=1e-6):
+    """bool[P, H]: hidden units whose pre-activation z lies within kappa * (|W1| |x| + |b1|) of
+    0, i.e. where a float32 evaluation of z may take the other side of the ReLU kink."""
+    _, a = forward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, return_all=True)
+    scale = np.abs(a["X"]) @ np.abs(np.asarray(W1, np.float64)).T + np.abs(np.asarray(b1, np.float64))
+    return np.abs(a["z"]) <= kappa * scale
+
+
+def backward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, grad_f, relu_mask=None):
     """Gradients of sum_p grad_f[p] * f[p] w.r.t. W1, b1, w2, b2 and the embeddings,
-    by the chain rule through the forward above (float64)."""
+    by the chain rule through the forward above (float64).  ``relu_mask`` (bool[P, H])
+    replaces the decision z > 0 of ReLU'(z) when given (a decision taken elsewhere)."""
     f, a = forward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, return_all=True)
     gf = np.asarray(grad_f, dtype=np.float64)
     g = a["g"]
@@ -73,7 +82,8 @@ def backward(emb, lens, vgene, self_scores, pairs, align, W1, b1, w2, b2, grad_f
     dw2 = a["h"].T @ u_bar
     db2 = np.array([u_bar.sum()])
     h_bar = u_bar[:, None] * np.asarray(w2, np.float64)[None, :]
-    z_bar = h_bar * (a["z"] > 0.0)
+    mask = (a["z"] > 0.0) if relu_mask is None else np.asarray(relu_mask, dtype=bool)
+    z_bar = h_bar * mask
     dW1 = z_bar.T @ a["X"]
     db1 = z_bar.sum(axis=0)
     x_bar = z_bar @ np.asarray(W1, np.float64)                                # [P, 4]

@@ -56,7 +56,7 @@ __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a
 // except z/h which are the lane's own hidden units).
 template <int NV, int UNITS>
 struct PairState {
-    float s, c, x2, x3, ni, nj, g, u;
+    float s, c, x2, x3, ni, nj, g, gm, u;
     bool ok;
     float z[UNITS];
 };
@@ -92,6 +92,7 @@ __device__ __forceinline__ void pair_forward(const GateIn &in, int64_t p, const 
     }
     st.u = group_sum(part) + b2;
     st.g = 1.f / (1.f + expf(-st.u));
+    st.gm = 1.f / (1.f + expf(st.u));  // 1 - g without cancellation
 }
 
 template <int UNITS>
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
         PairState<NV, UNITS> st;
         pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
         if (l == 0) {
-            fused[p] = st.c + st.g * (st.s - st.c);
+            fused[p] = st.g * st.s + st.gm * st.c;
             if (gate) gate[p] = st.g;
         }
     }
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
         PairState<NV, UNITS> st;
         pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
         const float gf = gfused[p];
-        const float ubar = gf * (st.s - st.c) * st.g * (1.f - st.g);
+        const float ubar = gf * (st.s - st.c) * st.g * st.gm;
         const float x[4] = {st.s, st.c, st.x2, st.x3};
         float xc = 0.f;
 #pragma unroll
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             xc += zbar * W1[k][1];
         }
         if (l == 0) ab2 += (double)ubar;
-        const float cbar = gf * (1.f - st.g) + group_sum(xc);
+        const float cbar = gf * st.gm + group_sum(xc);
         if (demb && st.ok) {
             const float inv = 1.f / (st.ni * st.nj);
             const float ci = st.c / (st.ni * st.ni), cj = st.c / (st.nj * st.nj);

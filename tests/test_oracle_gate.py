@@ -148,3 +148,29 @@ def test_contrastive_loss_gradient():
         fm[k] -= h
         fd = (gate.contrastive_loss(fp, y)[0] - gate.contrastive_loss(fm, y)[0]) / (2 * h)
         assert abs(fd - g[k]) < 1e-8
+
+
+def test_relu_mask_override(case):
+    """An explicit ReLU decision equal to z > 0 changes nothing; flipping one (pair, unit)
+    changes dW1 by exactly that unit's chain-rule term."""
+    a = dict(case)
+    a.pop("family")
+    gf = np.random.default_rng(3).standard_normal(case["pairs"].shape[0])
+    base = gate.backward(**a, grad_f=gf)
+    _, inter = gate.forward(**a, return_all=True)
+    mask = inter["z"] > 0
+    same = gate.backward(**a, grad_f=gf, relu_mask=mask)
+    for k in ("W1", "b1", "w2", "b2", "emb"):
+        assert np.array_equal(base[k], same[k])
+    p, k = 5, 3
+    flipped = mask.copy()
+    flipped[p, k] = ~flipped[p, k]
+    alt = gate.backward(**a, grad_f=gf, relu_mask=flipped)
+    g = inter["g"][p]
+    ubar = gf[p] * (inter["s"][p] - inter["c"][p]) * g * (1 - g)
+    term = ubar * case["w2"][k] * inter["X"][p]
+    sign = 1.0 if flipped[p, k] else -1.0
+    assert np.allclose(alt["W1"][k] - base["W1"][k], sign * term, rtol=1e-12, atol=1e-15)
+    amb = gate.relu_ambiguous(**a, kappa=1.0)
+    assert amb.all()                       # every unit is within 1x its own scale of zero
+    assert not gate.relu_ambiguous(**a, kappa=0.0).any() or (inter["z"] == 0).any()
