@@ -115,3 +115,62 @@ def contrastive_loss(f, y, margin: float = MARGIN):
     loss = (y * (1.0 - f) ** 2 + (1.0 - y) * hinge ** 2).sum() / P
     grad = (-2.0 * y * (1.0 - f) + 2.0 * (1.0 - y) * hinge) / P
     return loss, grad
+
+
+# ----------------------------------------------------------------------------- M channels
+#
+# Eq. (wm)/(afused) for M channels: one shared hidden layer, one logit per channel,
+#   z = W1 x + b1 (H), h = relu(z), g = W2 h + b2 (M), w = softmax(g), f = sum_m w_m a_m,
+# with channels a = (s, c, e) (alignment, embedding cosine, edit-distance similarity) and
+# features x = (s, c, e, |L_i - L_j|, [V_i == V_j]).  Reading: the paper's g^(m) share the
+# hidden layer of one two-layer MLP with M outputs.
+
+def forward_m(emb, lens, vgene, self_scores, pairs, align, edit_sim, W1, b1, W2, b2, return_all=False):
+    ft = features(emb, lens, vgene, self_scores, pairs, align)
+    e = np.asarray(edit_sim, dtype=np.float64)
+    A = np.stack([ft["s"], ft["c"], e], axis=1)                               # [P, 3]
+    X = np.stack([ft["s"], ft["c"], e, ft["delta"], ft["v"]], axis=1)        # [P, 5]
+    z = X @ np.asarray(W1, np.float64).T + np.asarray(b1, np.float64)[None, :]
+    h = np.maximum(z, 0.0)
+    g = h @ np.asarray(W2, np.float64).T + np.asarray(b2, np.float64)[None, :]  # [P, M]
+    g = g - g.max(axis=1, keepdims=True)
+    w = np.exp(g)
+    w /= w.sum(axis=1, keepdims=True)
+    f = (w * A).sum(axis=1)
+    if return_all:
+        return f, dict(ft, A=A, X=X, z=z, h=h, w=w)
+    return f
+
+
+def backward_m(emb, lens, vgene, self_scores, pairs, align, edit_sim, W1, b1, W2, b2, grad_f, relu_mask=None):
+    f, a = forward_m(emb, lens, vgene, self_scores, pairs, align, edit_sim, W1, b1, W2, b2, return_all=True)
+    gf = np.asarray(grad_f, dtype=np.float64)
+    w, A = a["w"], a["A"]
+    g_bar = gf[:, None] * w * (A - f[:, None])                                # d f / d g_m
+    dW2 = g_bar.T @ a["h"]
+    db2 = g_bar.sum(axis=0)
+    h_bar = g_bar @ np.asarray(W2, np.float64)
+    mask = (a["z"] > 0.0) if relu_mask is None else np.asarray(relu_mask, dtype=bool)
+    z_bar = h_bar * mask
+    dW1 = z_bar.T @ a["X"]
+    db1 = z_bar.sum(axis=0)
+    x_bar = z_bar @ np.asarray(W1, np.float64)                                # [P, 5]
+    c_bar = gf * w[:, 1] + x_bar[:, 1]
+    c_bar = np.where(a["ok"], c_bar, 0.0)
+    E = np.asarray(emb, dtype=np.float64)
+    i, j = a["i"], a["j"]
+    safe_i = np.where(a["ok"], a["ni"], 1.0)
+    safe_j = np.where(a["ok"], a["nj"], 1.0)
+    c = a["c"]
+    dc_dei = E[j] / (safe_i * safe_j)[:, None] - (c / safe_i ** 2)[:, None] * E[i]
+    dc_dej = E[i] / (safe_i * safe_j)[:, None] - (c / safe_j ** 2)[:, None] * E[j]
+    dE = np.zeros_like(E)
+    np.add.at(dE, i, c_bar[:, None] * dc_dei)
+    np.add.at(dE, j, c_bar[:, None] * dc_dej)
+    return dict(W1=dW1, b1=db1, W2=dW2, b2=db2, emb=dE, f=f)
+
+
+def relu_ambiguous_m(emb, lens, vgene, self_scores, pairs, align, edit_sim, W1, b1, W2, b2, kappa=1e-6):
+    _, a = forward_m(emb, lens, vgene, self_scores, pairs, align, edit_sim, W1, b1, W2, b2, return_all=True)
+    scale = np.abs(a["X"]) @ np.abs(np.asarray(W1, np.float64)).T + np.abs(np.asarray(b1, np.float64))
+    return np.abs(a["z"]) <= kappa * scale

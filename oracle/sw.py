@@ -42,6 +42,9 @@ def _lib():
     lib.oracle_minhash3.restype = None
     lib.oracle_minhash3.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+    lib.oracle_edit_pairs.restype = None
+    lib.oracle_edit_pairs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
     lib.oracle_sw_pairs.restype = None
     lib.oracle_sw_pairs.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,

@@ -66,3 +66,40 @@ void oracle_sw_pairs(const uint8_t *seqs, const int32_t *lens, int32_t stride,
                                  subst, gap_open, gap_extend);
     }
 }
+
+/*
+ * Weighted global edit distance (the paper's Appendix F.3 recurrence):
+ *   d[x][y] = min(d[x-1][y] + indel, d[x][y-1] + indel, d[x-1][y-1] + cost[a_x][b_y]),
+ *   d[x][0] = x * indel, d[0][y] = y * indel; result d[la][lb].
+ */
+int oracle_edit_distance(const uint8_t *a, int la, const uint8_t *b, int lb, const int8_t *cost, int indel)
+{
+    int cols = lb + 1;
+    int *d = (int *)malloc(sizeof(int) * (la + 1) * cols);
+    for (int x = 0; x <= la; ++x) {
+        for (int y = 0; y <= lb; ++y) {
+            int idx = x * cols + y;
+            if (x == 0) { d[idx] = y * indel; continue; }
+            if (y == 0) { d[idx] = x * indel; continue; }
+            int best = d[idx - cols] + indel;
+            int v = d[idx - 1] + indel;
+            if (v < best) best = v;
+            v = d[idx - cols - 1] + cost[a[x - 1] * 20 + b[y - 1]];
+            if (v < best) best = v;
+            d[idx] = best;
+        }
+    }
+    int out = d[la * cols + lb];
+    free(d);
+    return out;
+}
+
+void oracle_edit_pairs(const uint8_t *seqs, const int32_t *lens, int32_t stride, const int32_t *pairs, int64_t P,
+                       const int8_t *cost, int indel, int32_t *out)
+{
+    for (int64_t p = 0; p < P; ++p) {
+        int i = pairs[2 * p], j = pairs[2 * p + 1];
+        out[p] = oracle_edit_distance(seqs + (int64_t)i * stride, lens[i], seqs + (int64_t)j * stride, lens[j],
+                                      cost, indel);
+    }
+}
