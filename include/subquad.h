@@ -218,6 +218,42 @@ int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens
                      size_t ws_bytes, void *stream);
 
 /*
+ * subquad_edit_batch_ws -- the paper's own affinity recurrence (Appendix F.3), a weighted
+ * global edit distance, on every pair:
+ *   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost[a_x][b_y]),
+ *   D[x][0] = x * indel, D[0][y] = y * indel; dist[p] = D[L_i][L_j] (i32).
+ *   cost [20][20] i8 (device), symmetric, >= 0; 0 <= indel <= 1000.  The workspace is the
+ *   alignment one (subquad_align_workspace_bytes(P)).  Requires stride % 4 == 0, <= 64.
+ */
+int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                          const int32_t *pairs, int64_t P, const int8_t *cost, int32_t indel,
+                          int32_t *dist, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * subquad_gate3_fwd / subquad_gate3_bwd -- per-pair fusion over three channels, Sec. 3.6
+ * Eq. (wm) and (afused) with a softmax over M = 3 channel logits:
+ *   a = (s, c, e): s and c as in subquad_gate_fwd, e = 1 - dist[p] / (2 max(L_i, L_j))
+ *   (dist from subquad_edit_batch_ws with doubled costs);
+ *   x = (s, c, e, |L_i - L_j|, [V_i == V_j]); z = W1 x + b1; g = W2 relu(z) + b2;
+ *   w = softmax(g); fused[p] = sum_m w_m a_m; weights [P][3] (out, may be NULL): w.
+ *   W1 [H][5], b1 [H], W2 [3][H], b2 [3] f32; H in {16, 32, 64}; d % 4 == 0, d <= 512.
+ * The backward accumulates dW1, db1, dW2, db2 and (if non-NULL) demb exactly as
+ * subquad_gate_bwd does; ws: subquad_gate3_bwd_workspace_bytes(H) bytes, 256-byte aligned.
+ */
+int subquad_gate3_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                      const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                      const int32_t *align, const int32_t *dist, int64_t P, const float *W1,
+                      const float *b1, const float *W2, const float *b2, int32_t H, float *fused,
+                      float *weights, void *stream);
+size_t subquad_gate3_bwd_workspace_bytes(int32_t H);
+int subquad_gate3_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                      const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                      const int32_t *align, const int32_t *dist, int64_t P, const float *W1,
+                      const float *b1, const float *W2, const float *b2, int32_t H,
+                      const float *grad_fused, float *dW1, float *db1, float *dW2, float *db2,
+                      float *demb, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * subquad_graph_topk -- sparse similarity graph from the fused affinities (Algorithm 1,
  * graph construction; Sec. 3.7; the evaluation links receptors whose fused similarity
  * exceeds tau = 0.7, Appendix B sensitivity study).  Every pair (i, j) of `pairs` with

@@ -40,6 +40,13 @@ SIGNATURES = {
     "subquad_gate_bwd_workspace_bytes": (c_sz, [c_i32]),
     "subquad_gate_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "subquad_edit_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p, c_sz,
+                                             c_p]),
+    "subquad_gate3_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
+                                         c_p, c_p, c_i32, c_p, c_p, c_p]),
+    "subquad_gate3_bwd_workspace_bytes": (c_sz, [c_i32]),
+    "subquad_gate3_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
+                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "subquad_graph_workspace_bytes": (c_sz, [c_i64, c_i64]),
     "subquad_graph_topk": (ctypes.c_int, [c_p, c_p, c_i64, c_i64, ctypes.c_float, c_i32, c_p, c_sz, c_p, c_p,
                                           c_p, c_i64, c_p, c_p]),

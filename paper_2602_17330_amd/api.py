@@ -236,3 +236,67 @@ def graph_topk(pairs: torch.Tensor, w: torch.Tensor, n: int, tau: float = 0.7, k
     check(lib().subquad_graph_topk(_ptr(pairs), _ptr(w), P, n, float(tau), int(k), _ptr(ws), need, _ptr(rows),
                                    _ptr(cols), _ptr(vals), cap, ctypes.byref(nnz), _stream()))
     return rows, cols[: nnz.value], vals[: nnz.value]
+
+
+EDIT_INDEL = 2
+
+
+def edit_cost_matrix(subst) -> np.ndarray:
+    """Doubled substitution costs for the edit-distance channel: 0 for a match, 1 for a
+    substitution with a positive score (conservative), 2 otherwise; indels cost 2."""
+    S = np.asarray(subst.detach().cpu().numpy() if isinstance(subst, torch.Tensor) else subst, dtype=np.int64)
+    C = np.where(S > 0, 1, 2).astype(np.int8)
+    np.fill_diagonal(C, 0)
+    return C
+
+
+def edit_distance(seqs, lens, pairs, cost, indel: int = EDIT_INDEL, out=None, ws=None) -> torch.Tensor:
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    cost = _dev(cost, torch.int8, "cost")
+    P = pairs.shape[0]
+    if out is None:
+        out = torch.empty(P, dtype=torch.int32, device=seqs.device)
+    if P == 0:
+        return out
+    need = align_workspace_bytes(P)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=seqs.device)
+    check(lib().subquad_edit_batch_ws(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], _ptr(pairs), P,
+                                      _ptr(cost), indel, _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def _gate3_args(emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2):
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, W2, b2 = _gate_args(
+        emb, lens, vgene, self_s, pairs, align_s, W1, b1, W2, b2)
+    return emb, lens, vgene, self_s, pairs, align_s, _dev(dist, torch.int32, "dist"), W1, b1, W2, b2
+
+
+def gate3_fwd(emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2, return_weights=False, out=None):
+    emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2 = _gate3_args(
+        emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2)
+    P = pairs.shape[0]
+    fused = out if out is not None else torch.empty(P, dtype=torch.float32, device=emb.device)
+    wts = torch.empty((P, 3), dtype=torch.float32, device=emb.device) if return_weights else None
+    check(lib().subquad_gate3_fwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s),
+                                  _ptr(pairs), _ptr(align_s), _ptr(dist), P, _ptr(W1), _ptr(b1), _ptr(W2), _ptr(b2),
+                                  W1.shape[0], _ptr(fused), _ptr(wts), _stream()))
+    return (fused, wts) if return_weights else fused
+
+
+def gate3_bwd(emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2, grad_fused, need_emb=True):
+    emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2 = _gate3_args(
+        emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2)
+    gf = _dev(grad_fused, torch.float32, "grad_fused")
+    H = W1.shape[0]
+    grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(W2), torch.zeros_like(b2),
+             torch.zeros_like(emb) if need_emb else None)
+    need = int(lib().subquad_gate3_bwd_workspace_bytes(H))
+    ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
+    check(lib().subquad_gate3_bwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s),
+                                  _ptr(pairs), _ptr(align_s), _ptr(dist), pairs.shape[0], _ptr(W1), _ptr(b1),
+                                  _ptr(W2), _ptr(b2), H, _ptr(gf), *[_ptr(g) for g in grads], _ptr(ws), need,
+                                  _stream()))
+    return grads

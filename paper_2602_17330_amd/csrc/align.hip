@@ -167,11 +167,65 @@ __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la,
     return best;
 }
 
+// Weighted global edit distance of one pair in one lane (the paper's Appendix F.3
+// recurrence with caller-given substitution costs and indel cost):
+//   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost(a_x, b_y)).
+// a (the shorter sequence) runs down the unrolled rows, b across the column loop; the
+// answer D[la][lb] is picked out of the register column by an unrolled select.
+template <int ROWS>
+__device__ __forceinline__ int ed_lane(const uint8_t *__restrict__ arow, int la, const uint8_t *__restrict__ brow,
+                                       int lb, const uint32_t *__restrict__ C2, int indel) {
+    uint32_t idx2[ROWS / 2];
+#pragma unroll
+    for (int k = 0; k < ROWS / 2; ++k) {
+        int x0 = 2 * k, x1 = 2 * k + 1;
+        int c0 = x0 < la ? min((int)arow[x0], 19) : kMaskCode;
+        int c1 = x1 < la ? min((int)arow[x1], 19) : kMaskCode;
+        idx2[k] = (uint32_t)(c0 * kCodes + c1);
+    }
+    int D[ROWS];  // D[x] holds row x + 1 of the current column
+#pragma unroll
+    for (int x = 0; x < ROWS; ++x) D[x] = (x + 1) * indel;  // column 0
+    const uint32_t *bw = reinterpret_cast<const uint32_t *>(brow);
+    uint32_t word = bw[0];
+    for (int y0 = 0; y0 < lb; y0 += 4) {
+        uint32_t cur = word;
+        if (y0 + 4 < lb) word = bw[(y0 >> 2) + 1];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            const int y = y0 + k4;
+            if (y < lb) {
+                int c = min((int)((cur >> (8 * k4)) & 0xFFu), 19);
+                const uint32_t *col = C2 + c * (kCodes * kCodes);
+                int diag = y * indel;        // D[0][y]
+                int up = (y + 1) * indel;    // D[0][y+1]
+#pragma unroll
+                for (int k = 0; k < ROWS / 2; ++k) {
+                    uint32_t w = col[idx2[k]];
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int x = 2 * k + h2;
+                        const int cost = h2 ? (int)(w >> 16) : (int)(w & 0xFFFFu);
+                        int v = min(min(diag + cost, up + indel), D[x] + indel);
+                        diag = D[x];
+                        D[x] = v;
+                        up = v;
+                    }
+                }
+            }
+        }
+    }
+    int res = 0;
+#pragma unroll
+    for (int x = 0; x < ROWS; ++x) res = (x + 1 == la) ? D[x] : res;
+    return la == 0 ? lb * indel : res;
+}
+
 // Pairs of one rows bucket (shorter length in (ROWS-8, ROWS]), taken from the length-sorted
 // permutation: the bucket's range is read from the sort's end offsets on the device, so
 // the launch needs no host synchronisation.  Without a permutation (no workspace) every
 // pair is processed in input order with ROWS = the longest allowed row count.
-template <int ROWS>
+template <int ROWS, int MODE>
 __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__restrict__ seqs,
                                                               const int32_t *__restrict__ lens, int64_t n,
                                                               int32_t stride, const int32_t *__restrict__ pairs,
@@ -193,8 +247,14 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
         int c = e / (kCodes * kCodes);
         int rem = e - c * (kCodes * kCodes);
         int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
-        int s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : kMaskScore;
-        int s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : kMaskScore;
+        int s0, s1;
+        if (MODE == 0) {
+            s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : kMaskScore;
+            s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : kMaskScore;
+        } else {  // costs; rows past the end are never read back
+            s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : 0;
+            s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : 0;
+        }
         S2[e] = ((uint32_t)(uint16_t)(int16_t)s0) | ((uint32_t)(uint16_t)(int16_t)s1 << 16);
     }
     __syncthreads();
@@ -221,7 +281,8 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
             int la, lb;
             if (li <= lj) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
             else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
-            scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge);
+            if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge);
+            else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go);
         }
     }
 }
@@ -267,7 +328,8 @@ extern "C" int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int
 // The length sort needs P + 512 words of scratch; it is taken from a stream-ordered
 // allocation only when the caller passes no workspace (the plain entry point below).
 static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, const int32_t *pairs, int64_t P,
-                     const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st) {
+                     const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st,
+                     int mode = 0) {
     uint32_t *hist = scratch;
     uint32_t *perm = scratch + kAlignKeyBins;
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
@@ -283,11 +345,19 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64),
                                               (int64_t)device_cus() * knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU));
     const uint32_t *bin_end = hist;  // after the scatter, hist[k] is the end of bin k
-    {
+    if (mode == 0) {
         ProfScope prof("align_kernel", st);
-#define SQ_ROWS(R)                                                                                                   \
-    align_kernel<R><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, subst, \
-                                                                 go, ge, scores);
+#define SQ_ROWS(R)                                                                                             \
+    align_kernel<R, 0><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, \
+                                                                    subst, go, ge, scores);
+        SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
+        if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
+#undef SQ_ROWS
+    } else {
+        ProfScope prof("edit_kernel", st);
+#define SQ_ROWS(R)                                                                                             \
+    align_kernel<R, 1><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, \
+                                                                    subst, go, ge, scores);
         SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
         if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
 #undef SQ_ROWS
@@ -336,4 +406,21 @@ extern "C" int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int
     if (rc != SUBQUAD_OK) return rc;
     SQ_HIP(fe);
     return SUBQUAD_OK;
+}
+
+extern "C" int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                     const int32_t *pairs, int64_t P, const int8_t *cost, int32_t indel,
+                                     int32_t *dist, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0 && P >= 0, SUBQUAD_ERR_ARG, "n and P must be >= 0");
+    SQ_REQUIRE(P == 0 || (seqs && lens && pairs && cost && dist), SUBQUAD_ERR_ARG, "null pointer argument");
+    SQ_REQUIRE(stride >= 4 && stride <= 64 && stride % 4 == 0, SUBQUAD_ERR_ARG,
+               "stride must be a multiple of 4 in 4..64 (got %d)", stride);
+    SQ_REQUIRE(indel >= 0 && indel <= 1000, SUBQUAD_ERR_ARG, "indel must be in 0..1000");
+    SQ_REQUIRE(P < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "P must be below 2^32");
+    if (P == 0) return SUBQUAD_OK;
+    SQ_REQUIRE(ws && ws_bytes >= subquad_align_workspace_bytes(P), SUBQUAD_ERR_WORKSPACE,
+               "alignment workspace too small");
+    return align_run(seqs, lens, n, stride, pairs, P, cost, indel, 0, dist, static_cast<uint32_t *>(ws),
+                     as_stream(stream), 1);
 }

@@ -17,12 +17,9 @@
 // backward, the gradient of e_i stay in registers while the first index repeats.  Weight
 // gradients accumulate per lane in float64 and are reduced per block, then once per block
 // into a float64 workspace.
-#include "common.h"
+#include "gate_util.h"
 
 namespace subquad {
-
-constexpr int kGateThreads = 256;
-constexpr int kGroup = 16;
 
 struct GateIn {
     const float *emb;
@@ -33,24 +30,6 @@ struct GateIn {
     const float *W1, *b1, *w2, *b2;
     int32_t H;
 };
-
-__device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-    for (int off = kGroup / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kGroup);
-    return v;
-}
-
-template <int NV>
-__device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t row, int d4, int l, float4 (&v)[NV]) {
-    const float4 *r = reinterpret_cast<const float4 *>(emb) + row * d4;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        int c = l + kGroup * k;
-        v[k] = c < d4 ? r[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-}
-
-__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
 // Forward quantities of one pair (all lanes of the group hold the same values on return,
 // except z/h which are the lane's own hidden units).
@@ -314,12 +293,7 @@ static int gate_validate(const GateIn &in) {
     return SUBQUAD_OK;
 }
 
-static int64_t gate_blocks(int64_t P) {
-    // enough groups to fill the chip, each with a contiguous chunk of pairs
-    int64_t groups = std::max<int64_t>(
-        1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU)));
-    return ceil_div(groups, kGateThreads / kGroup);
-}
+static int64_t gate_blocks(int64_t P) { return gate_blocks_for(P, knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU)); }
 
 template <int NV>
 static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t st) {
