@@ -96,7 +96,8 @@ def gate_2p20(torch, sq, steps, warmup):
     args = (E, lens, vg, self_s, pairs, align, *W)
     fused = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
     grads = [torch.zeros_like(w) for w in W] + [torch.zeros_like(E)]
-    ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(api.gate_bwd_workspace_bytes(W[0].shape[0], pairs.shape[0]), dtype=torch.uint8,
+                     device="cuda")
     P = pairs.shape[0]
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]

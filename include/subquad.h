@@ -197,8 +197,9 @@ int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens
                      const float *w2, const float *b2, int32_t H, float *fused, float *gate,
                      void *stream);
 
-/* Bytes of device workspace subquad_gate_bwd needs for H hidden units. */
-size_t subquad_gate_bwd_workspace_bytes(int32_t H);
+/* Bytes of device workspace subquad_gate_bwd needs for H hidden units and P pairs
+ * (0 when H <= 0, P < 0 or P >= 2^32). */
+size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P);
 
 /*
  * subquad_gate_bwd -- gradient of L = sum_p grad_fused[p] * fused[p] (the backward of
@@ -206,9 +207,12 @@ size_t subquad_gate_bwd_workspace_bytes(int32_t H);
  * storing it.  Gradients ACCUMULATE into the outputs (zero them first for a plain
  * gradient): dW1 [H][4], db1 [H], dw2 [H], db2 [1], demb [n][d] (may be NULL: then the
  * embedding gradient is skipped).  The alignment, length and V-gene inputs get no gradient.
- * Weight gradients are reduced in float64; embedding gradients use float32 atomics, so
- * their summation order (and last bits) may vary between runs.
- *   ws / ws_bytes: at least subquad_gate_bwd_workspace_bytes(H) bytes, 256-byte aligned.
+ * Weight gradients are reduced in float64.  The embedding gradient is gathered in two
+ * passes over the pairs, stably sorted by i and then by j: a row whose pairs all fall in one
+ * worker's chunk is updated with a plain read-modify-write, a row split between chunks with
+ * float32 atomics (summation order, and last bits, may then vary between runs).  demb must
+ * be 16-byte aligned.
+ *   ws / ws_bytes: at least subquad_gate_bwd_workspace_bytes(H, P) bytes, 256-byte aligned.
  */
 int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
                      const int32_t *vgene, const int32_t *self, const int32_t *pairs,

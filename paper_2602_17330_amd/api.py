@@ -181,6 +181,13 @@ def gate_fwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, return_ga
     return (fused, gate) if return_gate else fused
 
 
+def gate_bwd_workspace_bytes(H: int, P: int) -> int:
+    need = int(lib().subquad_gate_bwd_workspace_bytes(int(H), int(P)))
+    if need == 0:
+        raise SubquadError(1, f"no gate workspace size for H={H}, P={P}")
+    return need
+
+
 def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fused,
              need_emb: bool = True, grads=None, ws: torch.Tensor | None = None):
     """Returns (dW1, db1, dw2, db2, demb); accumulates into ``grads`` when given."""
@@ -192,7 +199,7 @@ def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fuse
         grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(w2), torch.zeros_like(b2),
                  torch.zeros_like(emb) if need_emb else None)
     dW1, db1, dw2, db2, demb = grads
-    need = int(lib().subquad_gate_bwd_workspace_bytes(H))
+    need = gate_bwd_workspace_bytes(H, pairs.shape[0])
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
     check(lib().subquad_gate_bwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene),

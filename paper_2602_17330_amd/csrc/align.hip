@@ -59,52 +59,42 @@ __device__ __forceinline__ int align_key(int lmin, int lmax) {
     return (rb - 1) * 64 + (max(lmax, 1) - 1);
 }
 
-__global__ __launch_bounds__(256) void align_hist_kernel(const int32_t *__restrict__ pairs,
+__global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restrict__ pairs,
                                                          const int32_t *__restrict__ lens, int64_t n, int64_t P,
-                                                         uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[kAlignKeyBins];
-    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x) h[k] = 0;
-    __syncthreads();
+                                                         uint64_t *__restrict__ rec) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         int lmin = 1, lmax = 1;
         if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
-        atomicAdd(&h[align_key(lmin, lmax)], 1u);
+        rec[p] = ((uint64_t)align_key(lmin, lmax) << 32) | (uint64_t)p;
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x)
-        if (h[k]) atomicAdd(&hist[k], h[k]);
 }
 
-__global__ void align_zero_kernel(uint32_t *__restrict__ hist) {
-    for (int k = threadIdx.x; k < kAlignKeyBins; k += blockDim.x) hist[k] = 0;
+// bin_end[k] = number of sorted records with key <= k (one thread per key, binary search).
+__global__ __launch_bounds__(kAlignKeyBins) void align_bins_kernel(const uint64_t *__restrict__ srec, int64_t P,
+                                                                   uint32_t *__restrict__ bin_end) {
+    const uint64_t k = threadIdx.x;
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((srec[mid] >> 32) <= k) lo = mid + 1; else hi = mid;
+    }
+    bin_end[k] = (uint32_t)lo;
 }
 
-// Single block of 512 threads: exclusive scan of the 512 bins (in place).
-__global__ __launch_bounds__(kAlignKeyBins) void align_scan_kernel(uint32_t *__restrict__ hist) {
-    __shared__ uint32_t s[kAlignKeyBins];
-    const int t = threadIdx.x;
-    uint32_t v = hist[t];
-    s[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kAlignKeyBins; off <<= 1) {
-        uint32_t o = t >= off ? s[t - off] : 0;
-        __syncthreads();
-        s[t] += o;
-        __syncthreads();
-    }
-    hist[t] = s[t] - v;
-}
+struct AlignLayout {
+    size_t ra, rb, bins, radix, total;
+};
 
-__global__ __launch_bounds__(256) void align_scatter_kernel(const int32_t *__restrict__ pairs,
-                                                            const int32_t *__restrict__ lens, int64_t n, int64_t P,
-                                                            uint32_t *__restrict__ cursor,
-                                                            uint32_t *__restrict__ perm) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        int lmin = 1, lmax = 1;
-        if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
-        uint32_t pos = atomicAdd(&cursor[align_key(lmin, lmax)], 1u);
-        if ((int64_t)pos < P) perm[pos] = (uint32_t)p;
-    }
+static AlignLayout align_layout(int64_t P) {
+    AlignLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
+    L.ra = take(sizeof(uint64_t) * P);
+    L.rb = take(sizeof(uint64_t) * P);
+    L.bins = take(sizeof(uint32_t) * kAlignKeyBins);
+    L.radix = take(radix_scratch_bytes(P));
+    L.total = off;
+    return L;
 }
 
 // DP of one pair in one lane.  a: the shorter sequence (rows), b: the longer (columns).
@@ -229,7 +219,7 @@ template <int ROWS, int MODE>
 __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__restrict__ seqs,
                                                               const int32_t *__restrict__ lens, int64_t n,
                                                               int32_t stride, const int32_t *__restrict__ pairs,
-                                                              int64_t P, const uint32_t *__restrict__ perm,
+                                                              int64_t P, const uint64_t *__restrict__ perm,
                                                               const uint32_t *__restrict__ bin_end,
                                                               const int8_t *__restrict__ subst, int go, int ge,
                                                               int32_t *__restrict__ scores) {
@@ -267,7 +257,7 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
         bool valid = idx < hi;
         int64_t p = 0;
         if (valid) {
-            p = perm ? (int64_t)perm[idx] : idx;
+            p = perm ? (int64_t)(uint32_t)perm[idx] : idx;
             valid = p < P;
         }
         if (valid && !pair_ok(pairs, n, p)) {
@@ -302,11 +292,6 @@ __global__ __launch_bounds__(256) void self_scores_kernel(const uint8_t *__restr
     }
 }
 
-struct AlignScratch {
-    uint32_t *hist;
-    uint32_t *perm;
-};
-
 }  // namespace subquad
 
 using namespace subquad;
@@ -330,21 +315,26 @@ extern "C" int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int
 static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, const int32_t *pairs, int64_t P,
                      const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st,
                      int mode = 0) {
-    uint32_t *hist = scratch;
-    uint32_t *perm = scratch + kAlignKeyBins;
+    // Length sort: records (bucket key << 32 | p) sorted on their 9 key bits by the stable
+    // radix sort; then bin_end[k] = first position whose key exceeds k.
+    char *base = reinterpret_cast<char *>(scratch);
+    const AlignLayout L = align_layout(P);
+    uint64_t *ra = reinterpret_cast<uint64_t *>(base + L.ra);
+    uint64_t *rb = reinterpret_cast<uint64_t *>(base + L.rb);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(base + L.bins);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
-    align_zero_kernel<<<1, 512, 0, st>>>(hist);
-    SQ_LAUNCHED("align_zero_kernel");
-    align_hist_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, hist);
-    SQ_LAUNCHED("align_hist_kernel");
-    align_scan_kernel<<<1, kAlignKeyBins, 0, st>>>(hist);
-    SQ_LAUNCHED("align_scan_kernel");
-    align_scatter_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, hist, perm);
-    SQ_LAUNCHED("align_scatter_kernel");
+    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, ra);
+    SQ_LAUNCHED("align_keys_kernel");
+    uint64_t *sorted = nullptr;
+    int rc = radix_sort_u64(ra, rb, P, nullptr, 32, 9, base + L.radix, L.total - L.radix, st, &sorted, "sort_lengths");
+    if (rc != SUBQUAD_OK) return rc;
+    align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, hist);
+    SQ_LAUNCHED("align_bins_kernel");
+    uint64_t *perm = sorted;  // the pair index is the low word of each sorted record
     const int64_t waves = ceil_div(P, 64);
     const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64),
                                               (int64_t)device_cus() * knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU));
-    const uint32_t *bin_end = hist;  // after the scatter, hist[k] is the end of bin k
+    const uint32_t *bin_end = hist;
     if (mode == 0) {
         ProfScope prof("align_kernel", st);
 #define SQ_ROWS(R)                                                                                             \
@@ -368,7 +358,7 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
 
 extern "C" size_t subquad_align_workspace_bytes(int64_t P) {
     if (P < 0) return 0;
-    return align_up(sizeof(uint32_t) * (size_t)(P + kAlignKeyBins), 256);
+    return align_layout(std::max<int64_t>(P, 1)).total;
 }
 
 extern "C" int subquad_align_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,

@@ -18,6 +18,7 @@
 // gradients accumulate per lane in float64 and are reduced per block, then once per block
 // into a float64 workspace.
 #include "gate_util.h"
+#include "radix.h"
 
 namespace subquad {
 
@@ -130,15 +131,20 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
     }
 }
 
-// Workspace layout (doubles): dW1[H][4], db1[H], dw2[H], db2.
+// First pass of the backward, over the pairs in order of their first index i (order_i):
+// recomputes the forward, accumulates the weight gradients (float64 per lane, then per
+// block into wacc: dW1[H][4], db1[H], dw2[H], db2), accumulates e_i's gradient in registers
+// over its row, and stores pack[p] = (cbar, c, 1 / (|e_i||e_j|)) for the second pass.
 template <int NV, int UNITS>
 __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
-                                                                float *__restrict__ demb, double *__restrict__ wacc) {
+                                                                const uint64_t *__restrict__ order_i,
+                                                                float4 *__restrict__ pack, float *__restrict__ demb,
+                                                                double *__restrict__ wacc) {
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
     const int64_t chunk = ceil_div(in.P, ngroups);
-    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
     const int d4 = in.d >> 2;
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
@@ -155,32 +161,25 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float ni2 = 0.f;
     int64_t cur_i = -1;
-    auto flush_i = [&](int64_t row) {
-        if (!demb || row < 0) return;
-        float *base = demb + row * (int64_t)in.d;
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            int c = l + kGroup * k;
-            if (c < d4) {
-                atomicAdd(base + 4 * c + 0, gi[k].x);
-                atomicAdd(base + 4 * c + 1, gi[k].y);
-                atomicAdd(base + 4 * c + 2, gi[k].z);
-                atomicAdd(base + 4 * c + 3, gi[k].w);
-            }
-            gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-    };
-    for (int64_t p = p0; p < p1; ++p) {
+    bool started_here = false;
+    for (int64_t q = q0; q < q1; ++q) {
+        const uint64_t rec = order_i[q];
+        const int64_t p = (int64_t)(uint32_t)rec;
         const int64_t i = in.pairs[2 * p], j = in.pairs[2 * p + 1];
-        if (i < 0 || j < 0 || i >= in.n || j >= in.n) continue;  // out-of-range pair: skipped
+        if (i < 0 || j < 0 || i >= in.n || j >= in.n) {  // out-of-range pair: skipped
+            if (l == 0) pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            continue;
+        }
         if (i != cur_i) {
-            flush_i(cur_i);
+            if (cur_i >= 0 && demb) flush_row<NV>(demb, cur_i, d4, l, gi, started_here);
+            cur_i = i;
+            // The row starts inside this chunk unless the record before the chunk is in it too.
+            started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
             load_row<NV>(in.emb, i, d4, l, ei);
             float a = 0.f;
 #pragma unroll
             for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
             ni2 = group_sum(a);
-            cur_i = i;
         }
         load_row<NV>(in.emb, j, d4, l, ej);
         PairState<NV, UNITS> st;
@@ -195,33 +194,29 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             aw2[k] += (double)(ubar * h);
             const float zbar = st.z[k] > 0.f ? ubar * w2[k] : 0.f;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) aW1[k][q] += (double)(zbar * x[q]);
+            for (int qq = 0; qq < 4; ++qq) aW1[k][qq] += (double)(zbar * x[qq]);
             ab1[k] += (double)zbar;
             xc += zbar * W1[k][1];
         }
         if (l == 0) ab2 += (double)ubar;
         const float cbar = gf * st.gm + group_sum(xc);
+        const float inv = st.ok ? 1.f / (st.ni * st.nj) : 0.f;
+        if (l == 0) pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, 0.f);
         if (demb && st.ok) {
-            const float inv = 1.f / (st.ni * st.nj);
-            const float ci = st.c / (st.ni * st.ni), cj = st.c / (st.nj * st.nj);
-            float *bj = demb + j * (int64_t)in.d;
+            const float ci = st.c / (st.ni * st.ni);
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                int c = l + kGroup * k;
-                if (c < d4) {
-                    gi[k].x += cbar * (ej[k].x * inv - ci * ei[k].x);
-                    gi[k].y += cbar * (ej[k].y * inv - ci * ei[k].y);
-                    gi[k].z += cbar * (ej[k].z * inv - ci * ei[k].z);
-                    gi[k].w += cbar * (ej[k].w * inv - ci * ei[k].w);
-                    atomicAdd(bj + 4 * c + 0, cbar * (ei[k].x * inv - cj * ej[k].x));
-                    atomicAdd(bj + 4 * c + 1, cbar * (ei[k].y * inv - cj * ej[k].y));
-                    atomicAdd(bj + 4 * c + 2, cbar * (ei[k].z * inv - cj * ej[k].z));
-                    atomicAdd(bj + 4 * c + 3, cbar * (ei[k].w * inv - cj * ej[k].w));
-                }
+                gi[k].x += cbar * (ej[k].x * inv - ci * ei[k].x);
+                gi[k].y += cbar * (ej[k].y * inv - ci * ei[k].y);
+                gi[k].z += cbar * (ej[k].z * inv - ci * ei[k].z);
+                gi[k].w += cbar * (ej[k].w * inv - ci * ei[k].w);
             }
         }
     }
-    flush_i(cur_i);
+    if (cur_i >= 0 && demb) {
+        const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
+        flush_row<NV>(demb, cur_i, d4, l, gi, started_here && ends_here);
+    }
 
     // Block reduction of the weight gradients: lanes with equal l hold the same units.
     constexpr int kVals = 6 * UNITS;
@@ -229,7 +224,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
 #pragma unroll
     for (int k = 0; k < UNITS; ++k) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[k * 6 + q] = aW1[k][q];
+        for (int qq = 0; qq < 4; ++qq) v[k * 6 + qq] = aW1[k][qq];
         v[k * 6 + 4] = ab1[k];
         v[k * 6 + 5] = aw2[k];
     }
@@ -250,20 +245,20 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     __syncthreads();
     for (int e = threadIdx.x; e < kGroup * (kVals + 1); e += kGateThreads) {
         const int ll = e / (kVals + 1), m = e - ll * (kVals + 1);
-        double s = 0.0;
+        double sacc = 0.0;
 #pragma unroll
-        for (int ww = 0; ww < kGateThreads / 64; ++ww) s += red[ww][ll][m];
+        for (int ww = 0; ww < kGateThreads / 64; ++ww) sacc += red[ww][ll][m];
         if (m == kVals) {
-            if (ll == 0) atomicAdd(&wacc[in.H * 6], s);
+            if (ll == 0) atomicAdd(&wacc[in.H * 6], sacc);
             continue;
         }
-        const int k = m / 6, q = m - k * 6;
+        const int k = m / 6, qq = m - k * 6;
         const int unit = ll + kGroup * k;
         double *dst;
-        if (q < 4) dst = &wacc[unit * 4 + q];
-        else if (q == 4) dst = &wacc[in.H * 4 + unit];
+        if (qq < 4) dst = &wacc[unit * 4 + qq];
+        else if (qq == 4) dst = &wacc[in.H * 4 + unit];
         else dst = &wacc[in.H * 5 + unit];
-        atomicAdd(dst, s);
+        atomicAdd(dst, sacc);
     }
 }
 
@@ -313,20 +308,67 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
 }
 
 template <int NV>
-static int gate_bwd_nv(const GateIn &in, const float *gf, float *demb, double *wacc, hipStream_t st) {
+static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_i, const uint64_t *order_j, float4 *pack,
+                       float *demb, double *wacc, hipStream_t st) {
     const int64_t blocks = gate_blocks(in.P);
-    ProfScope prof("gate_bwd_kernel", st);
-    switch (in.H / kGroup) {
-#define SQ_CASE(U) \
-    case U: gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, demb, wacc); break;
-        SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
+    {
+        ProfScope prof("gate_bwd_kernel", st);
+        switch (in.H / kGroup) {
+#define SQ_CASE(U)                                                                                          \
+    case U:                                                                                                 \
+        gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, demb, wacc); \
+        break;
+            SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
 #undef SQ_CASE
-        default:
-            set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
-            return SUBQUAD_ERR_ARG;
+            default:
+                set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
+                return SUBQUAD_ERR_ARG;
+        }
     }
     SQ_LAUNCHED("gate_bwd_kernel");
+    if (demb) {
+        ProfScope prof("gate_cos_bwd_j_kernel", st);
+        gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, order_j,
+                                                                             pack, demb);
+    }
+    SQ_LAUNCHED("gate_cos_bwd_j_kernel");
     return SUBQUAD_OK;
+}
+
+struct GateBwdLayout {
+    size_t wacc, ra, rb, rc, rd, pack, radix, total;
+};
+
+static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P) {
+    GateBwdLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
+    L.wacc = take(sizeof(double) * (size_t)(H * 6 + 1));
+    L.ra = take(sizeof(uint64_t) * P);
+    L.rb = take(sizeof(uint64_t) * P);
+    L.rc = take(sizeof(uint64_t) * P);
+    L.rd = take(sizeof(uint64_t) * P);
+    L.pack = take(sizeof(float4) * P);
+    L.radix = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
+    L.total = off;
+    return L;
+}
+
+// Sorts the pair indices by their first and by their second index (stable, so each row
+// keeps the input order) for the two backward passes.
+static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws, const GateBwdLayout &L,
+                            hipStream_t st, uint64_t **order_i, uint64_t **order_j) {
+    uint64_t *ra = reinterpret_cast<uint64_t *>(ws + L.ra), *rb = reinterpret_cast<uint64_t *>(ws + L.rb);
+    uint64_t *rc = reinterpret_cast<uint64_t *>(ws + L.rc), *rd = reinterpret_cast<uint64_t *>(ws + L.rd);
+    const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 16);
+    const int bits = key_bits_for(n);
+    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 0, ra);
+    SQ_LAUNCHED("gate_order_keys_kernel");
+    int rc_ = radix_sort_u64(ra, rb, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, order_i, "sort_gate_i");
+    if (rc_ != SUBQUAD_OK) return rc_;
+    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 1, rc);
+    SQ_LAUNCHED("gate_order_keys_kernel");
+    return radix_sort_u64(rc, rd, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, order_j, "sort_gate_j");
 }
 
 }  // namespace subquad
@@ -352,9 +394,9 @@ extern "C" int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const in
     return gate_fwd_nv<16>(in, fused, gate, st);
 }
 
-extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H) {
-    if (H <= 0) return 0;
-    return align_up(sizeof(double) * (size_t)(H * 6 + 1), 256);
+extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P) {
+    if (H <= 0 || P < 0 || P >= (int64_t(1) << 32)) return 0;
+    return gate_bwd_layout(H, P).total;
 }
 
 extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens, const int32_t *vgene,
@@ -368,20 +410,28 @@ extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const in
     if (rc != SUBQUAD_OK) return rc;
     SQ_REQUIRE(dW1 && db1 && dw2 && db2, SUBQUAD_ERR_ARG, "null weight-gradient pointer");
     SQ_REQUIRE(P == 0 || grad_fused, SUBQUAD_ERR_ARG, "null grad_fused");
-    SQ_REQUIRE(ws && ws_bytes >= subquad_gate_bwd_workspace_bytes(H), SUBQUAD_ERR_WORKSPACE,
-               "gate workspace too small");
+    SQ_REQUIRE(P < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "P must be below 2^32");
+    const GateBwdLayout L = gate_bwd_layout(H, P);
+    SQ_REQUIRE(ws && ws_bytes >= L.total, SUBQUAD_ERR_WORKSPACE, "gate workspace of %zu bytes, %zu needed", ws_bytes,
+               L.total);
     SQ_REQUIRE(((uintptr_t)ws & 255) == 0, SUBQUAD_ERR_ARG, "workspace must be 256-byte aligned");
+    SQ_REQUIRE(demb == nullptr || ((uintptr_t)demb & 15) == 0, SUBQUAD_ERR_ARG, "demb must be 16-byte aligned");
     if (P == 0) return SUBQUAD_OK;
     hipStream_t st = as_stream(stream);
-    double *wacc = static_cast<double *>(ws);
+    char *w = static_cast<char *>(ws);
+    double *wacc = reinterpret_cast<double *>(w + L.wacc);
     gate_ws_zero_kernel<<<1, 256, 0, st>>>(wacc, H * 6 + 1);
     SQ_LAUNCHED("gate_ws_zero_kernel");
+    uint64_t *order_i = nullptr, *order_j = nullptr;
+    rc = gate_pair_orders(pairs, P, n, w, L, st, &order_i, &order_j);
+    if (rc != SUBQUAD_OK) return rc;
+    float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
     const int nv = (int)ceil_div(d / 4, kGroup);
-    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, demb, wacc, st);
-    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, demb, wacc, st);
-    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, demb, wacc, st);
-    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, demb, wacc, st);
-    else rc = gate_bwd_nv<16>(in, grad_fused, demb, wacc, st);
+    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
+    else rc = gate_bwd_nv<16>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
     if (rc != SUBQUAD_OK) return rc;
     gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, H, dW1, db1, dw2, db2);
     SQ_LAUNCHED("gate_ws_finish_kernel");

@@ -26,6 +26,112 @@ __device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t 
 
 __device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
 
+// Adds a row's accumulated gradient slice into demb.  A row whose pairs all lie inside one
+// group's chunk is owned by that group (plain read-modify-write); a row split across
+// chunks is added atomically.
+template <int NV>
+__device__ __forceinline__ void flush_row(float *__restrict__ demb, int64_t row, int d4, int l, float4 (&acc)[NV],
+                                          bool owned) {
+    float4 *base = reinterpret_cast<float4 *>(demb) + row * d4;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int c = l + kGroup * k;
+        if (c < d4) {
+            if (owned) {
+                float4 v = base[c];
+                v.x += acc[k].x;
+                v.y += acc[k].y;
+                v.z += acc[k].z;
+                v.w += acc[k].w;
+                base[c] = v;
+            } else {
+                float *f = reinterpret_cast<float *>(base + c);
+                atomicAdd(f + 0, acc[k].x);
+                atomicAdd(f + 1, acc[k].y);
+                atomicAdd(f + 2, acc[k].z);
+                atomicAdd(f + 3, acc[k].w);
+            }
+        }
+        acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// Second pass of the cosine gradient: pairs in order of their second index j; each row u
+// gathers its partners e_i and adds sum_p cbar_p (e_i inv_p - c_p e_u / |e_u|^2) to demb[u].
+// pack[p] = (cbar_p, c_p, inv_p = 1 / (|e_i| |e_j|), 0), written by the first pass.
+template <int NV>
+__global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const float *__restrict__ emb, int64_t n,
+                                                                      int32_t d, const int32_t *__restrict__ pairs,
+                                                                      int64_t P, const uint64_t *__restrict__ order_j,
+                                                                      const float4 *__restrict__ pack,
+                                                                      float *__restrict__ demb) {
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = ceil_div(P, ngroups);
+    const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
+    if (q0 >= q1) return;
+    const int d4 = d >> 2;
+    float4 eu[NV], ep[NV], acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float inv_nu2 = 0.f;
+    int64_t cur = -1;
+    bool started_here = false;
+    for (int64_t q = q0; q < q1; ++q) {
+        const uint64_t rec = order_j[q];
+        const int64_t u = (int64_t)(rec >> 32);
+        const int64_t p = (int64_t)(uint32_t)rec;
+        if (u != cur) {
+            if (cur >= 0 && cur < n) flush_row<NV>(demb, cur, d4, l, acc, started_here);
+            cur = u;
+            // The row starts inside this chunk unless the record before the chunk is in it too.
+            started_here = q0 == 0 || (int64_t)(order_j[q0 - 1] >> 32) != u;
+            if (u < n) {
+                load_row<NV>(emb, u, d4, l, eu);
+                float a = 0.f;
+#pragma unroll
+                for (int k = 0; k < NV; ++k) a += dot4(eu[k], eu[k]);
+                a = group_sum(a);
+                inv_nu2 = a > 0.f ? 1.f / a : 0.f;
+            }
+        }
+        if (u >= n || p >= P) continue;
+        const int64_t i = pairs[2 * p];
+        const float4 pk = pack[p];
+        if (pk.x == 0.f || i < 0 || i >= n) continue;
+        load_row<NV>(emb, i, d4, l, ep);
+        const float cu = pk.y * inv_nu2;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            acc[k].x += pk.x * (ep[k].x * pk.z - cu * eu[k].x);
+            acc[k].y += pk.x * (ep[k].y * pk.z - cu * eu[k].y);
+            acc[k].z += pk.x * (ep[k].z * pk.z - cu * eu[k].z);
+            acc[k].w += pk.x * (ep[k].w * pk.z - cu * eu[k].w);
+        }
+    }
+    if (cur >= 0 && cur < n) {
+        const bool ends_here = q1 == P || (int64_t)(order_j[q1] >> 32) != cur;
+        flush_row<NV>(demb, cur, d4, l, acc, started_here && ends_here);
+    }
+}
+
+// Records (key << 32 | p) for the pair-order sorts: key = pairs[p][side].
+static __global__ void gate_order_keys_kernel(const int32_t *__restrict__ pairs, int64_t P, int64_t n, int side,
+                                       uint64_t *__restrict__ rec) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = pairs[2 * p + side];
+        const uint64_t key = (k < 0 || k >= n) ? (uint64_t)n : (uint64_t)k;  // out of range sorts last
+        rec[p] = (key << 32) | (uint64_t)p;
+    }
+}
+
+inline int key_bits_for(int64_t n) {  // bits holding 0..n
+    int b = 1;
+    while ((int64_t(1) << b) <= n) ++b;
+    return b;
+}
+
 // Groups of 16 lanes, each owning a contiguous chunk of pairs.
 inline int64_t gate_blocks_for(int64_t P, int groups_per_cu) {
     int64_t groups = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * groups_per_cu));

@@ -61,6 +61,31 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     }
 }
 
+// Step 3a.  Runs: a record that starts a run of >= 2 records (equal mix bits, equal band)
+// appends (start << 32 | length) to the run list and adds its pair count.
+__device__ __forceinline__ bool same_bucket(uint64_t a, uint64_t c, uint32_t n32) {
+    return (a >> 32) == (c >> 32) && ((uint32_t)a / n32) == ((uint32_t)c / n32);
+}
+
+__global__ __launch_bounds__(256) void lsh_runs_kernel(const uint64_t *__restrict__ srec, int64_t total, int64_t n,
+                                                       uint64_t *__restrict__ runs, uint64_t *__restrict__ pcount,
+                                                       unsigned long long *__restrict__ counters) {
+    const uint32_t n32 = (uint32_t)n;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q + 1 < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t me = srec[q];
+        if (q > 0 && same_bucket(srec[q - 1], me, n32)) continue;  // not a run start
+        if (!same_bucket(srec[q + 1], me, n32)) continue;          // a run of one
+        int64_t m = 2;
+        while (q + m < total && same_bucket(srec[q + m], me, n32)) ++m;
+        const unsigned long long r = atomicAdd(&counters[0], 1ull);
+        runs[r] = ((uint64_t)q << 32) | (uint64_t)m;
+        const uint64_t pc = (uint64_t)m * (uint64_t)(m - 1) / 2;
+        pcount[r] = pc;
+        atomicAdd(&counters[1], (unsigned long long)pc);
+    }
+}
+
 __device__ __forceinline__ bool tuple_equal(const uint64_t *__restrict__ sig, int64_t M, int64_t i, int64_t j,
                                             int beta, int r) {
     const uint64_t *a = sig + i * M + (int64_t)beta * r;
@@ -70,43 +95,72 @@ __device__ __forceinline__ bool tuple_equal(const uint64_t *__restrict__ sig, in
     return eq;
 }
 
-// Step 3.  One thread per sorted record; the thread walks the rest of its run.
+// True when the tuples of i and j are equal in some band e < beta (fingerprints first,
+// signature words to confirm).
+__device__ __forceinline__ bool earlier_band(const uint64_t *__restrict__ sig, int64_t M, const uint8_t *__restrict__ F,
+                                             int b, int r, int64_t i, int64_t j, int beta) {
+    const uint8_t *Fi = F + i * b, *Fj = F + j * b;
+    if ((b & 3) == 0) {
+        const uint32_t *Wi = reinterpret_cast<const uint32_t *>(Fi);
+        const uint32_t *Wj = reinterpret_cast<const uint32_t *>(Fj);
+        for (int w = 0; 4 * w < beta; ++w) {
+            const uint32_t x = Wi[w] ^ Wj[w];
+            uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;  // flags equal bytes (and a few more)
+            const int live = beta - 4 * w;
+            if (live < 4) z &= (1u << (8 * live)) - 1u;
+            while (z) {
+                const int e = 4 * w + (__builtin_ctz(z) >> 3);
+                if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) return true;
+                z &= z - 1u;
+            }
+        }
+        return false;
+    }
+    for (int e = 0; e < beta; ++e)
+        if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) return true;
+    return false;
+}
+
+// Step 3b.  One thread per (run, x < y) pair of records, all runs flattened by the prefix
+// sum of their pair counts; k-th pair of a run: y = the largest y with y(y-1)/2 <= k,
+// x = k - y(y-1)/2.
 __global__ __launch_bounds__(1024) void lsh_emit_kernel(
-    const uint64_t *__restrict__ srec, int64_t total, int64_t n, const uint64_t *__restrict__ sig, int32_t M,
-    int32_t b, int32_t r, const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+    const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
+    const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+    const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const uint64_t me = srec[q];
-    const uint32_t hi = (uint32_t)(me >> 32);
-    const uint32_t lo = (uint32_t)me;
+    const int64_t nruns = (int64_t)counters[0];
+    const uint64_t visits = (uint64_t)counters[1];
     const uint32_t n32 = (uint32_t)n;
-    const int beta = (int)(lo / n32);
-    if (beta >= b) return;
-    const int64_t i = (int64_t)(lo - (uint32_t)beta * n32);
-    const int64_t rep_i = R > 1 ? rep_of(offs, R, i) : 0;
-    const uint8_t *Fi = F + i * b;
-    for (int64_t y = q + 1; y < total; ++y) {
-        const uint64_t other = srec[y];
-        if ((uint32_t)(other >> 32) != hi) break;
-        const uint32_t olo = (uint32_t)other;
-        const int obeta = (int)(olo / n32);
-        if (obeta != beta || obeta >= b) break;
-        const int64_t j = (int64_t)(olo - (uint32_t)obeta * n32);  // j > i within a run
-        if (R > 1 && rep_of(offs, R, j) != rep_i) continue;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < visits;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = nruns - 1;  // last run with poff <= t
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (poff[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const uint64_t run = runs[lo];
+        const uint64_t start = run >> 32;
+        const uint64_t k = t - poff[lo];
+        uint64_t y = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+        while (y * (y - 1) / 2 > k) --y;
+        while ((y + 1) * y / 2 <= k) ++y;
+        const uint64_t x = k - y * (y - 1) / 2;
+        const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
+        const int beta = (int)(la / n32);
+        if (beta >= b) continue;
+        const int64_t i = (int64_t)(la - (uint32_t)beta * n32);
+        const int64_t j = (int64_t)(lb - (uint32_t)beta * n32);  // i < j within a run
+        if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) continue;
         if (!tuple_equal(sig, M, i, j, beta, r)) continue;
-        const uint8_t *Fj = F + j * b;
-        bool earlier = false;
-        for (int e = 0; e < beta && !earlier; ++e)
-            if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) earlier = true;
-        if (earlier) continue;
-        unsigned long long slot = atomicAdd(count, 1ull);
+        if (earlier_band(sig, M, F, b, r, i, j, beta)) continue;
+        const unsigned long long slot = atomicAdd(count, 1ull);
         if ((int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
     }
 }
 
 __global__ void lsh_init_kernel(unsigned long long *count) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x < 4) count[threadIdx.x] = 0ull;  // pairs, runs, visits, spare
 }
 
 // Publishes P, the capacity status, and the clamped pair count used by the pair sort.
@@ -148,7 +202,7 @@ __global__ void lsh_rows_kernel(const uint64_t *__restrict__ skeys, const int64_
 }
 
 struct LshLayout {
-    size_t rec_a, rec_b, fp, pk_a, pk_b, misc, radix, total;
+    size_t rec_a, rec_b, fp, runs, poff, pk_a, pk_b, misc, radix, total;
 };
 
 static int bits_for(int64_t n) {
@@ -165,10 +219,12 @@ static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
     L.rec_a = take(sizeof(uint64_t) * recs);
     L.rec_b = take(sizeof(uint64_t) * recs);
     L.fp = take((size_t)recs);
+    L.runs = take(sizeof(uint64_t) * (recs / 2 + 1));
+    L.poff = take(sizeof(uint64_t) * (recs / 2 + 1));
     L.pk_a = take(sizeof(uint64_t) * cap);
     L.pk_b = take(sizeof(uint64_t) * cap);
-    L.misc = take(64);
-    L.radix = take(radix_scratch_bytes(std::max<int64_t>(recs, cap)));
+    L.misc = take(128);
+    L.radix = take(std::max(radix_scratch_bytes(std::max<int64_t>(recs, cap)), scan64_scratch_bytes(recs / 2 + 1)));
     L.total = off;
     return L;
 }
@@ -214,11 +270,23 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     uint64_t *sorted = nullptr;
     int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted, "sort_records");
     if (rc != SUBQUAD_OK) return rc;
+    uint64_t *runs = reinterpret_cast<uint64_t *>(ws + L.runs);
+    uint64_t *poff = reinterpret_cast<uint64_t *>(ws + L.poff);
+    unsigned long long *counters = count + 2;  // [0] runs, [1] pair visits
     const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
+    const int64_t grid = std::min<int64_t>(ceil_div(recs, emit_threads), (int64_t)device_cus() * 32);
+    {
+        ProfScope prof("lsh_runs_kernel", st);
+        lsh_runs_kernel<<<(unsigned)grid, 256, 0, st>>>(sorted, recs, n, runs, poff, counters);
+    }
+    SQ_LAUNCHED("lsh_runs_kernel");
+    rc = scan_exclusive_u64(poff, recs / 2 + 1, reinterpret_cast<const uint64_t *>(counters), rscratch, st);
+    if (rc != SUBQUAD_OK) return rc;
     {
         ProfScope prof("lsh_emit_kernel", st);
-        lsh_emit_kernel<<<(unsigned)ceil_div(recs, emit_threads), emit_threads, 0, st>>>(
-            sorted, recs, n, sig, M, b, r, F, offs, R, nb, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
+        lsh_emit_kernel<<<(unsigned)((int64_t)device_cus() * 16), emit_threads, 0, st>>>(
+            sorted, n, sig, M, b, r, F, offs, R, nb, runs, poff, counters,
+            reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
     }
     SQ_LAUNCHED("lsh_emit_kernel");
     return SUBQUAD_OK;
@@ -228,7 +296,7 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
 static int lsh_back(int64_t n, char *ws, const LshLayout &L, int64_t cap, int64_t sort_n, int nb, int32_t *pairs,
                     int64_t *row_offsets, int64_t *n_pairs_dev, int32_t *status_dev, hipStream_t st) {
     unsigned long long *count = reinterpret_cast<unsigned long long *>(ws + L.misc);
-    int64_t *clamped = reinterpret_cast<int64_t *>(ws + L.misc + 16);
+    int64_t *clamped = reinterpret_cast<int64_t *>(ws + L.misc + 64);
     lsh_count_kernel<<<1, 64, 0, st>>>(count, cap, n_pairs_dev, status_dev, clamped);
     SQ_LAUNCHED("lsh_count_kernel");
     uint64_t *sorted = reinterpret_cast<uint64_t *>(ws + L.pk_a);

@@ -25,4 +25,9 @@ int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev
 size_t scan_scratch_bytes(int64_t count);
 int scan_exclusive_u32(uint32_t *data, int64_t count, void *scratch, hipStream_t st);
 
+// In-place exclusive prefix sum of 64-bit values; the count of values is read from
+// count_dev when non-null (bounded by count_cap).
+size_t scan64_scratch_bytes(int64_t count_cap);
+int scan_exclusive_u64(uint64_t *data, int64_t count_cap, const uint64_t *count_dev, void *scratch, hipStream_t st);
+
 }  // namespace subquad

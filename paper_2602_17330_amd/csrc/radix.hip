@@ -106,6 +106,101 @@ int scan_exclusive_u32(uint32_t *data, int64_t count, void *scratch, hipStream_t
     return SUBQUAD_OK;
 }
 
+// ---- 64-bit exclusive scan (device-side element count) ----
+__device__ __forceinline__ uint64_t block_inclusive_scan64(uint64_t v, uint64_t *wave_tot) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) wave_tot[w] = v;
+    __syncthreads();
+    uint64_t add = 0;
+    for (int k = 0; k < w; ++k) add += wave_tot[k];
+    __syncthreads();
+    return v + add;
+}
+
+__device__ __forceinline__ int64_t count_of(int64_t cap, const uint64_t *count_dev) {
+    if (!count_dev) return cap;
+    uint64_t c = *count_dev;
+    return c < (uint64_t)cap ? (int64_t)c : cap;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan64_reduce_kernel(const uint64_t *__restrict__ data, int64_t cap,
+                                                                     const uint64_t *__restrict__ count_dev,
+                                                                     uint64_t *__restrict__ partial) {
+    __shared__ uint64_t wt[4];
+    const int64_t count = count_of(cap, count_dev);
+    int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (idx < count) s += data[idx];
+    }
+    uint64_t inc = block_inclusive_scan64(s, wt);
+    if (threadIdx.x == kScanThreads - 1) partial[blockIdx.x] = inc;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan64_partials_kernel(uint64_t *__restrict__ partial, int64_t m) {
+    __shared__ uint64_t wt[4];
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < m; base += kScanThreads) {
+        int64_t idx = base + threadIdx.x;
+        uint64_t v = idx < m ? partial[idx] : 0;
+        uint64_t inc = block_inclusive_scan64(v, wt);
+        uint64_t carry = carry_s;
+        if (idx < m) partial[idx] = carry + inc - v;
+        __syncthreads();
+        if (threadIdx.x == kScanThreads - 1) carry_s = carry + inc;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan64_apply_kernel(uint64_t *__restrict__ data, int64_t cap,
+                                                                    const uint64_t *__restrict__ count_dev,
+                                                                    const uint64_t *__restrict__ partial) {
+    __shared__ uint64_t wt[4];
+    const int64_t count = count_of(cap, count_dev);
+    int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    uint64_t v[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        v[k] = idx < count ? data[idx] : 0;
+        s += v[k];
+    }
+    uint64_t inc = block_inclusive_scan64(s, wt);
+    uint64_t run = partial[blockIdx.x] + inc - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t idx = base + k;
+        if (idx < count) data[idx] = run;
+        run += v[k];
+    }
+}
+
+size_t scan64_scratch_bytes(int64_t count_cap) {
+    return align_up(sizeof(uint64_t) * (size_t)std::max<int64_t>(1, ceil_div(count_cap, kScanChunk)), 256);
+}
+
+int scan_exclusive_u64(uint64_t *data, int64_t count_cap, const uint64_t *count_dev, void *scratch, hipStream_t st) {
+    if (count_cap <= 0) return SUBQUAD_OK;
+    int64_t chunks = ceil_div(count_cap, kScanChunk);
+    uint64_t *partial = static_cast<uint64_t *>(scratch);
+    scan64_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
+    SQ_LAUNCHED("scan64_reduce_kernel");
+    scan64_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks);
+    SQ_LAUNCHED("scan64_partials_kernel");
+    scan64_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
+    SQ_LAUNCHED("scan64_apply_kernel");
+    return SUBQUAD_OK;
+}
+
 __device__ __forceinline__ int64_t live_count(int64_t n_cap, const int64_t *n_dev) {
     if (!n_dev) return n_cap;
     int64_t v = *n_dev;

@@ -64,7 +64,7 @@ class Pipeline:
         self.scores = torch.empty(cap, dtype=torch.int32, device=dev)
         self.fused = torch.empty(cap, dtype=torch.float32, device=dev)
         self.align_ws = torch.empty(api.align_workspace_bytes(cap), dtype=torch.uint8, device=dev)
-        self.gate_ws = torch.empty(int(lib().subquad_gate_bwd_workspace_bytes(self.W[0].shape[0])),
+        self.gate_ws = torch.empty(api.gate_bwd_workspace_bytes(self.W[0].shape[0], cap),
                                    dtype=torch.uint8, device=dev)
         self.grads = [torch.zeros_like(w) for w in self.W] + [torch.zeros_like(self.emb)]
 

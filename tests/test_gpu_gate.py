@@ -196,3 +196,25 @@ def test_gate_2p20_pairs_full_size():
         ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
         assert ok, (name, rel)
     check_ambiguous_pairs(full, amb, gf_full)
+
+
+def test_backward_hub_rows():
+    """Rows shared by thousands of pairs (on either side) span many workers' chunks, so both
+    passes mix owned rows (plain update) with rows split between chunks (atomics)."""
+    rep = synth.tiny(n_families=60, fam_size=8, seed=21)
+    c = make_case(rep, 64, 64, 6000, seed=21)
+    pairs = c["pairs"].copy()
+    pairs[:2500, 0] = 3                       # hub as first index
+    pairs[2500:4500, 1] = 7                   # hub as second index
+    pairs[4500:4600] = [11, 11]               # self pairs
+    c = dict(c, pairs=pairs, align=sw_oracle(rep.seqs, rep.lens, pairs, synth.load_blosum62()))
+    full = c
+    c, amb = split_ambiguous(full)
+    gf = synth.upstream_grad(c["pairs"].shape[0], seed=21)
+    say(f"gate bwd hub rows (ambiguous ReLU pairs set aside: {len(amb)})")
+    grads = sq.gate_bwd(*gpu_args(c), dev(gf))
+    torch.cuda.synchronize()
+    ref = ogate.backward(**oracle_args(c), grad_f=gf)
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
+        assert ok, (name, rel)
