@@ -321,7 +321,13 @@ def main():
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),
         "gate_fwd_kernel": ("hbm", P * (2 * d * 4 + 16)),
-        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 2 * d * 4 + 20)),
+        # backward, 2*d*4 + 16 (recompute) + 2*d*4 (dE) bytes per pair, split over its two
+        # passes: rows by i write e_i's gradient, rows by j write e_j's
+        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 16 + d * 4)),
+        "gate_cos_bwd_j_kernel": ("hbm", P * d * 4),
+        "sort_gate_i_scatter": ("hbm", 2 * P * 8),
+        "sort_gate_j_scatter": ("hbm", 2 * P * 8),
+        "sort_lengths_scatter": ("hbm", 2 * P * 8),
         "align_kernel": ("alu", cells * SW_OPS_PER_CELL),
     }
     kernels = {}
