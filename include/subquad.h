@@ -275,6 +275,37 @@ int subquad_graph_topk(const int32_t *pairs, const float *w, int64_t P, int64_t 
                        int32_t k, void *ws, size_t ws_bytes, int64_t *row_offsets, int32_t *cols,
                        float *vals, int64_t cap, int64_t *nnz, void *stream);
 
+/*
+ * Prototype-contrastive loss (Sec. 3, prototype-contrastive consolidation; Eq. (pc), (proto)):
+ *   p_c = mean of the rows of emb with label c (S_c);
+ *   loss = sum over x in the batch of  log sum_{c : S_c non-empty} exp(<e_x, p_c> / tau)
+ *                                    - <e_x, p_{y(x)}> / tau.
+ * The denominator runs over every non-empty class, the positive one included.
+ *   emb [n][d] f32 (16-byte aligned), d in {32, 64, 128}; labels [n] i32, classes 0..C-1
+ *   (a row with a label outside that range belongs to no class); batch [B] i32 row indices
+ *   (repeats allowed; an index outside [0, n) or of an unlabelled row contributes nothing);
+ *   tau > 0.  Logits are float32 matrix-core products; per-row log-sum-exp in float32; the
+ *   sum over the batch in float64 in a fixed order.
+ * subquad_proto_fwd: loss [1] f64 (device, out); row_loss [B] f32 (device, out, may be NULL);
+ *   protos [C][d] f32 (device, out, may be NULL): the prototypes.  It leaves the prototypes,
+ *   class sizes and per-row log-sum-exp in ws.
+ * subquad_proto_bwd: ACCUMULATES grad_loss * d loss / d emb into demb [n][d] (16-byte
+ *   aligned); grad_loss is a device f32 scalar (NULL: 1).  It reads what subquad_proto_fwd
+ *   left in ws: call it with the same inputs and the same, unmodified ws.  With
+ *   through_prototypes != 0 the gradient also flows through Eq. (pc) into every labelled row;
+ *   with 0 the prototypes are held constant.  Batch-row gradients are added with float32
+ *   atomics (summation order, and last bits, may vary between runs).
+ *   ws / ws_bytes: at least subquad_proto_workspace_bytes(n, d, C, B) bytes, 256-byte aligned.
+ */
+size_t subquad_proto_workspace_bytes(int64_t n, int32_t d, int64_t C, int64_t B);
+int subquad_proto_fwd(const float *emb, int64_t n, int32_t d, const int32_t *labels, int64_t C,
+                      const int32_t *batch, int64_t B, float tau, double *loss, float *row_loss,
+                      float *protos, void *ws, size_t ws_bytes, void *stream);
+int subquad_proto_bwd(const float *emb, int64_t n, int32_t d, const int32_t *labels, int64_t C,
+                      const int32_t *batch, int64_t B, float tau, const float *grad_loss,
+                      int32_t through_prototypes, float *demb, void *ws, size_t ws_bytes,
+                      void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -307,3 +307,46 @@ def gate3_bwd(emb, lens, vgene, self_s, pairs, align_s, dist, W1, b1, W2, b2, gr
                                   _ptr(W2), _ptr(b2), H, _ptr(gf), *[_ptr(g) for g in grads], _ptr(ws), need,
                                   _stream()))
     return grads
+
+
+PROTO_TAU = 0.1
+
+
+class ProtoLoss:
+    """Prototype-contrastive loss over an embedding table (Eq. (pc), Eq. (proto)); the forward
+    keeps its workspace for the backward that follows it."""
+
+    def __init__(self, n: int, d: int, C: int, B: int, device="cuda"):
+        self.n, self.d, self.C, self.B = n, d, C, B
+        need = int(lib().subquad_proto_workspace_bytes(n, d, C, B))
+        if need == 0:
+            raise SubquadError(1, f"no proto workspace size for n={n}, d={d}, C={C}, B={B}")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def _check(self, emb, labels, batch):
+        emb = _dev(emb, torch.float32, "emb")
+        labels = _dev(labels, torch.int32, "labels")
+        batch = _dev(batch, torch.int32, "batch")
+        if emb.shape != (self.n, self.d) or labels.shape[0] != self.n or batch.shape[0] != self.B:
+            raise SubquadError(1, "shapes do not match the ProtoLoss sizes")
+        return emb, labels, batch
+
+    def forward(self, emb, labels, batch, tau: float = PROTO_TAU, row_loss: bool = False, protos: bool = False):
+        emb, labels, batch = self._check(emb, labels, batch)
+        rl = torch.empty(self.B, dtype=torch.float32, device=emb.device) if row_loss else None
+        P = torch.empty((self.C, self.d), dtype=torch.float32, device=emb.device) if protos else None
+        check(lib().subquad_proto_fwd(_ptr(emb), self.n, self.d, _ptr(labels), self.C, _ptr(batch), self.B, tau,
+                                      _ptr(self.loss), _ptr(rl), _ptr(P), _ptr(self.ws), self.ws.numel(), _stream()))
+        return self.loss, rl, P
+
+    def backward(self, emb, labels, batch, tau: float = PROTO_TAU, grad_loss=None, through_prototypes=True,
+                 demb=None):
+        emb, labels, batch = self._check(emb, labels, batch)
+        if demb is None:
+            demb = torch.zeros_like(emb)
+        gl = None if grad_loss is None else _dev(grad_loss, torch.float32, "grad_loss")
+        check(lib().subquad_proto_bwd(_ptr(emb), self.n, self.d, _ptr(labels), self.C, _ptr(batch), self.B, tau,
+                                      _ptr(gl), int(bool(through_prototypes)), _ptr(demb), _ptr(self.ws),
+                                      self.ws.numel(), _stream()))
+        return demb

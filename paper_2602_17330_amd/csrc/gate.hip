@@ -32,25 +32,53 @@ struct GateIn {
     int32_t H;
 };
 
+// One pair's inputs as loaded by a group: the rows, the integer features and e_j.
+template <int NV>
+struct PairLoad {
+    int64_t p, i, j;  // i < 0: no pair (past the chunk, or out of range)
+    float s, x2, x3;
+    float4 ej[NV];
+};
+
+template <int NV>
+__device__ __forceinline__ void load_pair(const GateIn &in, int64_t p, int64_t i, int64_t j, int d4, int l,
+                                          PairLoad<NV> &pl) {
+    pl.p = p;
+    const bool ok = p >= 0 && i >= 0 && j >= 0 && i < in.n && j < in.n;
+    pl.i = ok ? i : -1;
+    pl.j = ok ? j : -1;
+    if (!ok) return;
+    const float si = (float)in.self[i], sj = (float)in.self[j];
+    pl.s = (float)in.align[p] / sqrtf(si * sj);
+    pl.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
+    pl.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
+    load_row<NV>(in.emb, j, d4, l, pl.ej);
+}
+
+// Pre-activation of one hidden unit as one fixed fma chain, so that every kernel that
+// evaluates it takes the same ReLU decision bit for bit.
+__device__ __forceinline__ float unit_preact(const float (&w)[4], float b, float s, float c, float x2, float x3) {
+    return fmaf(w[3], x3, fmaf(w[2], x2, fmaf(w[1], c, fmaf(w[0], s, b))));
+}
+
 // Forward quantities of one pair (all lanes of the group hold the same values on return,
-// except z/h which are the lane's own hidden units).
-template <int NV, int UNITS>
+// except z, the lane's own hidden units).
+template <int UNITS>
 struct PairState {
-    float s, c, x2, x3, ni, nj, g, gm, u;
+    float c, ni, nj, g, gm, u;
     bool ok;
     float z[UNITS];
 };
 
 template <int NV, int UNITS>
-__device__ __forceinline__ void pair_forward(const GateIn &in, int64_t p, const float4 (&ei)[NV], float ni2,
-                                             const float4 (&ej)[NV], int64_t i, int64_t j,
+__device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, const PairLoad<NV> &pl,
                                              const float (&W1)[UNITS][4], const float (&b1)[UNITS],
-                                             const float (&w2)[UNITS], float b2, PairState<NV, UNITS> &st) {
+                                             const float (&w2)[UNITS], float b2, PairState<UNITS> &st) {
     float dot = 0.f, nj2 = 0.f;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        dot += dot4(ei[k], ej[k]);
-        nj2 += dot4(ej[k], ej[k]);
+        dot += dot4(ei[k], pl.ej[k]);
+        nj2 += dot4(pl.ej[k], pl.ej[k]);
     }
     dot = group_sum(dot);
     nj2 = group_sum(nj2);
@@ -59,16 +87,11 @@ __device__ __forceinline__ void pair_forward(const GateIn &in, int64_t p, const 
     const float den = st.ni * st.nj;
     st.ok = den >= 1e-12f;
     st.c = st.ok ? dot / den : 0.f;
-    const float si = (float)in.self[i], sj = (float)in.self[j];
-    st.s = (float)in.align[p] / sqrtf(si * sj);
-    st.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
-    st.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
     float part = 0.f;
 #pragma unroll
     for (int k = 0; k < UNITS; ++k) {
-        float z = W1[k][0] * st.s + W1[k][1] * st.c + W1[k][2] * st.x2 + W1[k][3] * st.x3 + b1[k];
-        st.z[k] = z;
-        part += w2[k] * fmaxf(z, 0.f);
+        st.z[k] = unit_preact(W1[k], b1[k], pl.s, st.c, pl.x2, pl.x3);
+        part += w2[k] * fmaxf(st.z[k], 0.f);
     }
     st.u = group_sum(part) + b2;
     st.g = 1.f / (1.f + expf(-st.u));
@@ -89,6 +112,15 @@ __device__ __forceinline__ void load_weights(const GateIn &in, int l, float (&W1
     b2 = in.b2[0];
 }
 
+template <int NV>
+__device__ __forceinline__ void load_row_norm(const GateIn &in, int64_t i, int d4, int l, float4 (&ei)[NV], float &ni2) {
+    load_row<NV>(in.emb, i, d4, l, ei);
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
+    ni2 = group_sum(a);
+}
+
 template <int NV, int UNITS>
 __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float *__restrict__ fused,
                                                                 float *__restrict__ gate) {
@@ -101,51 +133,148 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
     const int d4 = in.d >> 2;
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
-    float4 ei[NV], ej[NV];
+    float4 ei[NV];
     float ni2 = 0.f;
     int64_t cur_i = -1;
-    for (int64_t p = p0; p < p1; ++p) {
-        const int64_t i = in.pairs[2 * p], j = in.pairs[2 * p + 1];
-        if (i < 0 || j < 0 || i >= in.n || j >= in.n) {  // out-of-range pair: no access
-            if (l == 0) {
-                fused[p] = __builtin_nanf("");
-                if (gate) gate[p] = __builtin_nanf("");
-            }
-            continue;
-        }
-        if (i != cur_i) {
-            load_row<NV>(in.emb, i, d4, l, ei);
-            float a = 0.f;
+    for (int64_t p = p0; p < p1; p += kGateBatch) {
+        int64_t ib[kGateBatch], jb[kGateBatch];
 #pragma unroll
-            for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
-            ni2 = group_sum(a);
-            cur_i = i;
+        for (int u = 0; u < kGateBatch; ++u) {
+            ib[u] = p + u < p1 ? in.pairs[2 * (p + u)] : -1;
+            jb[u] = p + u < p1 ? in.pairs[2 * (p + u) + 1] : -1;
         }
-        load_row<NV>(in.emb, j, d4, l, ej);
-        PairState<NV, UNITS> st;
-        pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
-        if (l == 0) {
-            fused[p] = st.g * st.s + st.gm * st.c;
-            if (gate) gate[p] = st.g;
+        PairLoad<NV> pl[kGateBatch];
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) load_pair<NV>(in, p + u < p1 ? p + u : -1, ib[u], jb[u], d4, l, pl[u]);
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) {
+            if (p + u >= p1) break;
+            if (pl[u].i < 0) {  // out-of-range pair: no access
+                if (l == 0) {
+                    fused[p + u] = __builtin_nanf("");
+                    if (gate) gate[p + u] = __builtin_nanf("");
+                }
+                continue;
+            }
+            if (pl[u].i != cur_i) {
+                load_row_norm<NV>(in, pl[u].i, d4, l, ei, ni2);
+                cur_i = pl[u].i;
+            }
+            PairState<UNITS> st;
+            pair_forward<NV, UNITS>(ei, ni2, pl[u], W1, b1, w2, b2, st);
+            if (l == 0) {
+                fused[p + u] = st.g * pl[u].s + st.gm * st.c;
+                if (gate) gate[p + u] = st.g;
+            }
         }
     }
 }
 
 // First pass of the backward, over the pairs in order of their first index i (order_i):
-// recomputes the forward, accumulates the weight gradients (float64 per lane, then per
-// block into wacc: dW1[H][4], db1[H], dw2[H], db2), accumulates e_i's gradient in registers
-// over its row, and stores pack[p] = (cbar, c, 1 / (|e_i||e_j|)) for the second pass.
+// recomputes the forward, accumulates e_i's gradient in registers over its row, and stores
+// per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
+// feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
 template <int NV, int UNITS>
 __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
                                                                 const uint64_t *__restrict__ order_i,
-                                                                float4 *__restrict__ pack, float *__restrict__ demb,
-                                                                double *__restrict__ wacc) {
+                                                                float4 *__restrict__ pack, float4 *__restrict__ feat,
+                                                                float *__restrict__ demb) {
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
     const int64_t chunk = ceil_div(in.P, ngroups);
     const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
+    if (q0 >= q1) return;
     const int d4 = in.d >> 2;
+    float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
+    load_weights<UNITS>(in, l, W1, b1, w2, b2);
+    float4 ei[NV], gi[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    float ni2 = 0.f;
+    int64_t cur_i = -1;
+    bool started_here = false;
+    for (int64_t q = q0; q < q1; q += kGateBatch) {
+        int64_t pb[kGateBatch], ib[kGateBatch], jb[kGateBatch];
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) pb[u] = q + u < q1 ? (int64_t)(uint32_t)order_i[q + u] : -1;
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) {
+            ib[u] = pb[u] >= 0 ? in.pairs[2 * pb[u]] : -1;
+            jb[u] = pb[u] >= 0 ? in.pairs[2 * pb[u] + 1] : -1;
+        }
+        PairLoad<NV> pl[kGateBatch];
+        float gfb[kGateBatch];
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) {
+            load_pair<NV>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
+            gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) {
+            if (pb[u] < 0) break;
+            const int64_t p = pb[u];
+            if (pl[u].i < 0) {  // out-of-range pair: skipped
+                if (l == 0) {
+                    pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    feat[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                continue;
+            }
+            const int64_t i = pl[u].i;
+            if (i != cur_i) {
+                if (cur_i >= 0 && demb) flush_row<NV>(demb, cur_i, d4, l, gi, started_here);
+                cur_i = i;
+                // The row starts inside this chunk unless the record before the chunk is in it too.
+                started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
+                load_row_norm<NV>(in, i, d4, l, ei, ni2);
+            }
+            PairState<UNITS> st;
+            pair_forward<NV, UNITS>(ei, ni2, pl[u], W1, b1, w2, b2, st);
+            const float gf = gfb[u];
+            const float ubar = gf * (pl[u].s - st.c) * st.g * st.gm;
+            float xc = 0.f;
+#pragma unroll
+            for (int k = 0; k < UNITS; ++k) xc += st.z[k] > 0.f ? W1[k][1] * w2[k] : 0.f;
+            const float cbar = gf * st.gm + ubar * group_sum(xc);
+            const float inv = st.ok ? 1.f / (st.ni * st.nj) : 0.f;
+            if (l == 0) {
+                pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
+                feat[p] = make_float4(pl[u].s, st.c, pl[u].x2, pl[u].x3);
+            }
+            if (demb && st.ok) {
+                const float ci = st.c / (st.ni * st.ni);
+#pragma unroll
+                for (int k = 0; k < NV; ++k) {
+                    gi[k].x += cbar * (pl[u].ej[k].x * inv - ci * ei[k].x);
+                    gi[k].y += cbar * (pl[u].ej[k].y * inv - ci * ei[k].y);
+                    gi[k].z += cbar * (pl[u].ej[k].z * inv - ci * ei[k].z);
+                    gi[k].w += cbar * (pl[u].ej[k].w * inv - ci * ei[k].w);
+                }
+            }
+        }
+    }
+    if (cur_i >= 0 && demb) {
+        const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
+        flush_row<NV>(demb, cur_i, d4, l, gi, started_here && ends_here);
+    }
+}
+
+// Weight gradients from the per-pair record of the first pass (a stream of 32 bytes per
+// pair, no gathers): with ubar = dL/du and z = W1 x + b1 recomputed from x,
+//   dW1[k] += ubar w2_k [z_k > 0] x,  db1[k] += ubar w2_k [z_k > 0],
+//   dw2[k] += ubar relu(z_k),          db2 += ubar.
+// Lane l of a 16-lane group owns units l + 16 m; float64 accumulators, reduced per block and
+// added into wacc (dW1[H][4], db1[H], dw2[H], db2).
+template <int UNITS>
+__global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, const float4 *__restrict__ pack,
+                                                                  const float4 *__restrict__ feat,
+                                                                  double *__restrict__ wacc) {
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = ceil_div(in.P, ngroups);
+    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
     double aW1[UNITS][4], ab1[UNITS], aw2[UNITS], ab2 = 0.0;
@@ -156,69 +285,31 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
 #pragma unroll
         for (int q = 0; q < 4; ++q) aW1[k][q] = 0.0;
     }
-    float4 ei[NV], ej[NV], gi[NV];
+    for (int64_t pb = p0; pb < p1; pb += kGroup) {
+        // lane t of the group loads pair pb + t; the group then walks the 16 pairs
+        const int64_t mine = pb + l;
+        const float4 f = mine < p1 ? feat[mine] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float ub = mine < p1 ? pack[mine].w : 0.f;
+        const int cnt = (int)min((int64_t)kGroup, p1 - pb);
+        for (int t = 0; t < cnt; ++t) {
+            const float s = __shfl(f.x, t, kGroup), c = __shfl(f.y, t, kGroup);
+            const float x2 = __shfl(f.z, t, kGroup), x3 = __shfl(f.w, t, kGroup);
+            const float ubar = __shfl(ub, t, kGroup);
+            const float x[4] = {s, c, x2, x3};
 #pragma unroll
-    for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    float ni2 = 0.f;
-    int64_t cur_i = -1;
-    bool started_here = false;
-    for (int64_t q = q0; q < q1; ++q) {
-        const uint64_t rec = order_i[q];
-        const int64_t p = (int64_t)(uint32_t)rec;
-        const int64_t i = in.pairs[2 * p], j = in.pairs[2 * p + 1];
-        if (i < 0 || j < 0 || i >= in.n || j >= in.n) {  // out-of-range pair: skipped
-            if (l == 0) pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-            continue;
-        }
-        if (i != cur_i) {
-            if (cur_i >= 0 && demb) flush_row<NV>(demb, cur_i, d4, l, gi, started_here);
-            cur_i = i;
-            // The row starts inside this chunk unless the record before the chunk is in it too.
-            started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
-            load_row<NV>(in.emb, i, d4, l, ei);
-            float a = 0.f;
+            for (int k = 0; k < UNITS; ++k) {
+                const float z = unit_preact(W1[k], b1[k], s, c, x2, x3);
+                aw2[k] += (double)(ubar * fmaxf(z, 0.f));
+                const float zbar = z > 0.f ? ubar * w2[k] : 0.f;
 #pragma unroll
-            for (int k = 0; k < NV; ++k) a += dot4(ei[k], ei[k]);
-            ni2 = group_sum(a);
-        }
-        load_row<NV>(in.emb, j, d4, l, ej);
-        PairState<NV, UNITS> st;
-        pair_forward<NV, UNITS>(in, p, ei, ni2, ej, i, j, W1, b1, w2, b2, st);
-        const float gf = gfused[p];
-        const float ubar = gf * (st.s - st.c) * st.g * st.gm;
-        const float x[4] = {st.s, st.c, st.x2, st.x3};
-        float xc = 0.f;
-#pragma unroll
-        for (int k = 0; k < UNITS; ++k) {
-            const float h = fmaxf(st.z[k], 0.f);
-            aw2[k] += (double)(ubar * h);
-            const float zbar = st.z[k] > 0.f ? ubar * w2[k] : 0.f;
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) aW1[k][qq] += (double)(zbar * x[qq]);
-            ab1[k] += (double)zbar;
-            xc += zbar * W1[k][1];
-        }
-        if (l == 0) ab2 += (double)ubar;
-        const float cbar = gf * st.gm + group_sum(xc);
-        const float inv = st.ok ? 1.f / (st.ni * st.nj) : 0.f;
-        if (l == 0) pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, 0.f);
-        if (demb && st.ok) {
-            const float ci = st.c / (st.ni * st.ni);
-#pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                gi[k].x += cbar * (ej[k].x * inv - ci * ei[k].x);
-                gi[k].y += cbar * (ej[k].y * inv - ci * ei[k].y);
-                gi[k].z += cbar * (ej[k].z * inv - ci * ei[k].z);
-                gi[k].w += cbar * (ej[k].w * inv - ci * ei[k].w);
+                for (int qq = 0; qq < 4; ++qq) aW1[k][qq] += (double)(zbar * x[qq]);
+                ab1[k] += (double)zbar;
             }
+            if (l == 0) ab2 += (double)ubar;
         }
-    }
-    if (cur_i >= 0 && demb) {
-        const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
-        flush_row<NV>(demb, cur_i, d4, l, gi, started_here && ends_here);
     }
 
-    // Block reduction of the weight gradients: lanes with equal l hold the same units.
+    // Block reduction: lanes with equal l hold the same units.
     constexpr int kVals = 6 * UNITS;
     double v[kVals];
 #pragma unroll
@@ -309,23 +400,29 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
 
 template <int NV>
 static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_i, const uint64_t *order_j, float4 *pack,
-                       float *demb, double *wacc, hipStream_t st) {
+                       float4 *feat, float *demb, double *wacc, hipStream_t st) {
     const int64_t blocks = gate_blocks(in.P);
-    {
-        ProfScope prof("gate_bwd_kernel", st);
-        switch (in.H / kGroup) {
-#define SQ_CASE(U)                                                                                          \
-    case U:                                                                                                 \
-        gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, demb, wacc); \
-        break;
-            SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
-#undef SQ_CASE
-            default:
-                set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
-                return SUBQUAD_ERR_ARG;
-        }
+    switch (in.H / kGroup) {
+#define SQ_CASE(U)                                                                                                 \
+    case U: {                                                                                                      \
+        {                                                                                                          \
+            ProfScope prof("gate_bwd_kernel", st);                                                                 \
+            gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, feat, demb);   \
+        }                                                                                                          \
+        SQ_LAUNCHED("gate_bwd_kernel");                                                                            \
+        {                                                                                                          \
+            ProfScope prof("gate_wgrad_kernel", st);                                                               \
+            gate_wgrad_kernel<U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, pack, feat, wacc);                 \
+        }                                                                                                          \
+        SQ_LAUNCHED("gate_wgrad_kernel");                                                                          \
+        break;                                                                                                     \
     }
-    SQ_LAUNCHED("gate_bwd_kernel");
+        SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
+#undef SQ_CASE
+        default:
+            set_error("H = %d is not one of 16, 32, 64, 128, 256", in.H);
+            return SUBQUAD_ERR_ARG;
+    }
     if (demb) {
         ProfScope prof("gate_cos_bwd_j_kernel", st);
         gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, order_j,
@@ -336,7 +433,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_
 }
 
 struct GateBwdLayout {
-    size_t wacc, ra, rb, rc, rd, pack, radix, total;
+    size_t wacc, ra, rb, rc, rd, pack, feat, radix, total;
 };
 
 static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P) {
@@ -349,6 +446,7 @@ static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P) {
     L.rc = take(sizeof(uint64_t) * P);
     L.rd = take(sizeof(uint64_t) * P);
     L.pack = take(sizeof(float4) * P);
+    L.feat = take(sizeof(float4) * P);
     L.radix = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
     L.total = off;
     return L;
@@ -426,12 +524,13 @@ extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const in
     rc = gate_pair_orders(pairs, P, n, w, L, st, &order_i, &order_j);
     if (rc != SUBQUAD_OK) return rc;
     float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
+    float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
     const int nv = (int)ceil_div(d / 4, kGroup);
-    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
-    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
-    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
-    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
-    else rc = gate_bwd_nv<16>(in, grad_fused, order_i, order_j, pack, demb, wacc, st);
+    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
+    else rc = gate_bwd_nv<16>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
     if (rc != SUBQUAD_OK) return rc;
     gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, H, dW1, db1, dw2, db2);
     SQ_LAUNCHED("gate_ws_finish_kernel");

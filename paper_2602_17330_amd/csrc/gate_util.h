@@ -7,6 +7,9 @@ namespace subquad {
 
 constexpr int kGateThreads = 256;
 constexpr int kGroup = 16;
+// Pairs whose index and row loads a lane group issues together before computing any of
+// them: more gathers in flight per group.
+constexpr int kGateBatch = 4;
 
 __device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
@@ -72,42 +75,58 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
     if (q0 >= q1) return;
     const int d4 = d >> 2;
-    float4 eu[NV], ep[NV], acc[NV];
+    float4 eu[NV], acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float inv_nu2 = 0.f;
     int64_t cur = -1;
     bool started_here = false;
-    for (int64_t q = q0; q < q1; ++q) {
-        const uint64_t rec = order_j[q];
-        const int64_t u = (int64_t)(rec >> 32);
-        const int64_t p = (int64_t)(uint32_t)rec;
-        if (u != cur) {
-            if (cur >= 0 && cur < n) flush_row<NV>(demb, cur, d4, l, acc, started_here);
-            cur = u;
-            // The row starts inside this chunk unless the record before the chunk is in it too.
-            started_here = q0 == 0 || (int64_t)(order_j[q0 - 1] >> 32) != u;
-            if (u < n) {
-                load_row<NV>(emb, u, d4, l, eu);
-                float a = 0.f;
+    for (int64_t qb = q0; qb < q1; qb += kGateBatch) {
+        int64_t ub[kGateBatch], ib[kGateBatch];
+        float4 pk[kGateBatch];
 #pragma unroll
-                for (int k = 0; k < NV; ++k) a += dot4(eu[k], eu[k]);
-                a = group_sum(a);
-                inv_nu2 = a > 0.f ? 1.f / a : 0.f;
-            }
+        for (int t = 0; t < kGateBatch; ++t) {
+            const uint64_t rec = qb + t < q1 ? order_j[qb + t] : ~0ull;
+            ub[t] = qb + t < q1 ? (int64_t)(rec >> 32) : -1;
+            const int64_t p = (int64_t)(uint32_t)rec;
+            const bool live = ub[t] >= 0 && ub[t] < n && p < P;
+            pk[t] = live ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+            ib[t] = live ? pairs[2 * p] : -1;
         }
-        if (u >= n || p >= P) continue;
-        const int64_t i = pairs[2 * p];
-        const float4 pk = pack[p];
-        if (pk.x == 0.f || i < 0 || i >= n) continue;
-        load_row<NV>(emb, i, d4, l, ep);
-        const float cu = pk.y * inv_nu2;
+        float4 ep[kGateBatch][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            acc[k].x += pk.x * (ep[k].x * pk.z - cu * eu[k].x);
-            acc[k].y += pk.x * (ep[k].y * pk.z - cu * eu[k].y);
-            acc[k].z += pk.x * (ep[k].z * pk.z - cu * eu[k].z);
-            acc[k].w += pk.x * (ep[k].w * pk.z - cu * eu[k].w);
+        for (int t = 0; t < kGateBatch; ++t) {
+            const bool use = pk[t].x != 0.f && ib[t] >= 0 && ib[t] < n;
+            if (!use) ib[t] = -1;
+            if (use) load_row<NV>(emb, ib[t], d4, l, ep[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kGateBatch; ++t) {
+            if (ub[t] < 0) break;
+            const int64_t u = ub[t];
+            if (u != cur) {
+                if (cur >= 0 && cur < n) flush_row<NV>(demb, cur, d4, l, acc, started_here);
+                cur = u;
+                // The row starts inside this chunk unless the record before the chunk is in it too.
+                started_here = q0 == 0 || (int64_t)(order_j[q0 - 1] >> 32) != u;
+                if (u < n) {
+                    load_row<NV>(emb, u, d4, l, eu);
+                    float a = 0.f;
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) a += dot4(eu[k], eu[k]);
+                    a = group_sum(a);
+                    inv_nu2 = a > 0.f ? 1.f / a : 0.f;
+                }
+            }
+            if (ib[t] < 0) continue;
+            const float cu = pk[t].y * inv_nu2;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                acc[k].x += pk[t].x * (ep[t][k].x * pk[t].z - cu * eu[k].x);
+                acc[k].y += pk[t].x * (ep[t][k].y * pk[t].z - cu * eu[k].y);
+                acc[k].z += pk[t].x * (ep[t][k].z * pk[t].z - cu * eu[k].z);
+                acc[k].w += pk[t].x * (ep[t][k].w * pk[t].z - cu * eu[k].w);
+            }
         }
     }
     if (cur >= 0 && cur < n) {

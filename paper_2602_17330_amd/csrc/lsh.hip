@@ -76,8 +76,23 @@ __global__ __launch_bounds__(256) void lsh_runs_kernel(const uint64_t *__restric
         const uint64_t me = srec[q];
         if (q > 0 && same_bucket(srec[q - 1], me, n32)) continue;  // not a run start
         if (!same_bucket(srec[q + 1], me, n32)) continue;          // a run of one
-        int64_t m = 2;
-        while (q + m < total && same_bucket(srec[q + m], me, n32)) ++m;
+        // The bucket's records are contiguous: gallop forward from q + 1, then bisect, so a
+        // run of m records costs O(log m) loads instead of m.
+        int64_t good = q + 1, bad = total, stride = 1;
+        while (good + stride < total) {
+            if (!same_bucket(srec[good + stride], me, n32)) {
+                bad = good + stride;
+                break;
+            }
+            good += stride;
+            stride <<= 1;
+        }
+        while (bad - good > 1) {
+            const int64_t mid = good + ((bad - good) >> 1);
+            if (same_bucket(srec[mid], me, n32)) good = mid;
+            else bad = mid;
+        }
+        const int64_t m = bad - q;
         const unsigned long long r = atomicAdd(&counters[0], 1ull);
         runs[r] = ((uint64_t)q << 32) | (uint64_t)m;
         const uint64_t pc = (uint64_t)m * (uint64_t)(m - 1) / 2;

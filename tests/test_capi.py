@@ -118,3 +118,14 @@ def test_knobs(L):
     assert L.subquad_set_knob(2, 0) == 0 and L.subquad_get_knob(2) == 64
     assert L.subquad_set_knob(3, 100) == 1            # not a multiple of 64
     assert L.subquad_set_knob(9, 1) == 1 and L.subquad_get_knob(9) == -1
+
+
+def test_proto_validation(L):
+    ws = L.subquad_proto_workspace_bytes(100, 64, 10, 50)
+    assert ws > 0 and L.subquad_proto_workspace_bytes(100, 64, 0, 50) == 0
+    args = [FAKE, 100, 64, FAKE, 10, FAKE, 50, ctypes.c_float(0.1)]
+    assert L.subquad_proto_fwd(*args, FAKE, NULL, NULL, 4096, ws - 1, NULL) == 5         # short workspace
+    assert L.subquad_proto_fwd(*args[:2], 48, *args[3:], FAKE, NULL, NULL, 4096, ws, NULL) == 1  # d
+    assert L.subquad_proto_fwd(*args[:-1], ctypes.c_float(0.0), FAKE, NULL, NULL, 4096, ws, NULL) == 1  # tau
+    assert L.subquad_proto_fwd(*args, NULL, NULL, NULL, 4096, ws, NULL) == 1             # null loss
+    assert L.subquad_proto_bwd(*args, NULL, 1, NULL, 4096, ws, NULL) == 1                # null demb
