@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # int32 VALU lane-ops per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-SW_OPS_PER_CELL = 8  # int32 VALU operations of one Gotoh cell update
+# int32 VALU operations of one folded Gotoh cell update: E and F (two max3 with the extend
+# and open terms), diagonal + substitution, H = max3, running max, and the two clamps at 0
+SW_OPS_PER_CELL = 8
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak
 
 
 def parse():
@@ -42,8 +45,10 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
+    ap.add_argument("--no-proto", action="store_true", help="skip the prototype-loss measurement")
     ap.add_argument("--calib-copy", type=int, default=0,
-                    help="also run N device copies of 1 GiB (counter calibration)")
+                    help="also run N elementwise copies of 1 GiB (y = x * 1 over 2^28 float32: 1 GiB read, "
+                         "1 GiB written) to calibrate the HBM byte counters")
     return ap.parse_args()
 
 
@@ -136,6 +141,57 @@ def gate_2p20(torch, sq, steps, warmup):
                 fwd_eff_GBs=P * 1040 / (f_ms / 1e3) / 1e9, bwd_eff_GBs=P * 2064 / (b_ms / 1e3) / 1e9,
                 workload="2^20 pairs sampled from the candidates of the 100,000-sequence Zipf "
                          "repertoire, d=128, H=64, fp32")
+
+
+def proto_leg(torch, sq, rep, emb, steps, warmup):
+    """Prototype-contrastive loss (Eq. pc, Eq. proto) forward and backward through the
+    prototypes over the bench table: n rows, C = its families, a batch of 65,536 rows
+    (seed 78), d = 128, tau = 0.1.  Matrix-core work per step: 2BCd (forward logits) +
+    4BCd (batch-row backward: logits again, then G P) + 4BCd (prototype backward: logits
+    again, then G^T E)."""
+    import synth
+    from paper_2602_17330_amd import _lib, api
+    labels = rep.family.astype(np.int32)
+    C = int(labels.max()) + 1
+    B = 65536
+    batch = synth.sample_rows(rep.n, B, seed=78).astype(np.int32)
+    E = api.to_device(emb)
+    Y = api.to_device(labels)
+    Bt = api.to_device(batch)
+    d = emb.shape[1]
+    pl = api.ProtoLoss(rep.n, d, C, B)
+    demb = torch.zeros_like(E)
+
+    def one():
+        pl.forward(E, Y, Bt)
+        pl.backward(E, Y, Bt, demb=demb)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kern = _lib.profile_report()
+    _lib.profile_enable(False)
+    bcd = 2.0 * B * C * d
+    flops = {"proto_fwd_kernel": bcd, "proto_bwd_rows_kernel": 2 * bcd, "proto_bwd_protos_kernel": 2 * bcd}
+    kernels = {}
+    for name, (launches, total_ms) in kern.items():
+        avg = total_ms / max(launches, 1)
+        e = {"launches_per_step": launches / steps, "avg_launch_ms": avg}
+        if name in flops:
+            tf = flops[name] / (avg / 1e3) / 1e12
+            e.update(bound="mfma", achieved=tf, peak=MFMA_F32_PEAK_TFLOPS, unit="TFLOP/s",
+                     frac=tf / MFMA_F32_PEAK_TFLOPS, alg_flops_per_launch=flops[name])
+        kernels[name] = e
+    total_flops = 5 * bcd
+    return dict(workload=f"{rep.n} rows, C={C} classes (families), B={B}, d={d}, tau=0.1, fp32 MFMA",
+                step_ms=wall * 1e3, rows_per_s=B / wall, tflops_step=total_flops / wall / 1e12,
+                kernels=kernels)
 
 
 def cpu_baseline(rep, emb, S, pipe, cfg):
@@ -352,11 +408,12 @@ def main():
     sw_gcups = kernels.get("align_kernel", {}).get("gcups")
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
+    proto = None if a.no_proto else proto_leg(torch, sq, rep, emb, max(3, min(a.steps, 5)), 1)
     if a.calib_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(a.calib_copy):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
     cpu = None if a.no_cpu_baseline else cpu_baseline(rep, emb, S, pipe, cfg)
 
@@ -380,6 +437,7 @@ def main():
         "sw_kernel_gcups": sw_gcups,
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
         "gate_2p20": gate,
+        "proto_loss": proto,
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -36,6 +37,21 @@ int device_cus() {
         cache[dev] = cus;
     }
     return cache[dev];
+}
+
+int resident_blocks_per_cu(const void *kernel) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    cache.emplace(kernel, nb);
+    return nb;
 }
 
 // One thread per row: bit 0 = bad length, bit 1 = bad residue; counts go to out[0], out[1].

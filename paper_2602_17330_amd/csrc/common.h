@@ -52,6 +52,9 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Number of compute units of the current device (cached per process per device).
 int device_cus();
 
+// Blocks of 256 threads that one CU holds at once for `kernel` (cached per kernel).
+int resident_blocks_per_cu(const void *kernel);
+
 // Launch-shape knob value (default when unset).
 int knob(int which);
 

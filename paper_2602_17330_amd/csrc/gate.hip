@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     const int d4 = in.d >> 2;
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
-    float4 ei[NV], gi[NV];
+    float4 ei[NV], gi[NV], old[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float ni2 = 0.f;
@@ -223,10 +223,11 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             }
             const int64_t i = pl[u].i;
             if (i != cur_i) {
-                if (cur_i >= 0 && demb) flush_row<NV>(demb, cur_i, d4, l, gi, started_here);
+                if (cur_i >= 0 && demb) flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here);
                 cur_i = i;
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
+                if (demb) load_grad_row<NV>(demb, i, d4, l, old);
                 load_row_norm<NV>(in, i, d4, l, ei, ni2);
             }
             PairState<UNITS> st;
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     }
     if (cur_i >= 0 && demb) {
         const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
-        flush_row<NV>(demb, cur_i, d4, l, gi, started_here && ends_here);
+        flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here && ends_here);
     }
 }
 
@@ -379,15 +380,19 @@ static int gate_validate(const GateIn &in) {
     return SUBQUAD_OK;
 }
 
-static int64_t gate_blocks(int64_t P) { return gate_blocks_for(P, knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU)); }
+static int64_t gate_blocks(int64_t P, const void *kernel) {
+    return gate_blocks_resident(P, knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU), kernel);
+}
 
 template <int NV>
 static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t st) {
-    const int64_t blocks = gate_blocks(in.P);
     ProfScope prof("gate_fwd_kernel", st);
     switch (in.H / kGroup) {
-#define SQ_CASE(U) \
-    case U: gate_fwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, fused, gate); break;
+#define SQ_CASE(U)                                                                                                \
+    case U:                                                                                                       \
+        gate_fwd_kernel<NV, U><<<(unsigned)gate_blocks(in.P, (const void *)gate_fwd_kernel<NV, U>), kGateThreads, 0, \
+                                 st>>>(in, fused, gate);                                                          \
+        break;
         SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
 #undef SQ_CASE
         default:
@@ -401,16 +406,17 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
 template <int NV>
 static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_i, const uint64_t *order_j, float4 *pack,
                        float4 *feat, float *demb, double *wacc, hipStream_t st) {
-    const int64_t blocks = gate_blocks(in.P);
     switch (in.H / kGroup) {
 #define SQ_CASE(U)                                                                                                 \
     case U: {                                                                                                      \
         {                                                                                                          \
+            const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U>);                        \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
             gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, feat, demb);   \
         }                                                                                                          \
         SQ_LAUNCHED("gate_bwd_kernel");                                                                            \
         {                                                                                                          \
+            const int64_t blocks = gate_blocks(in.P, (const void *)gate_wgrad_kernel<U>);                          \
             ProfScope prof("gate_wgrad_kernel", st);                                                               \
             gate_wgrad_kernel<U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, pack, feat, wacc);                 \
         }                                                                                                          \
@@ -424,6 +430,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_
             return SUBQUAD_ERR_ARG;
     }
     if (demb) {
+        const int64_t blocks = gate_blocks(in.P, (const void *)gate_cos_bwd_j_kernel<NV>);
         ProfScope prof("gate_cos_bwd_j_kernel", st);
         gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, order_j,
                                                                              pack, demb);

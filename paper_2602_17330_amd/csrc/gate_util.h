@@ -59,6 +59,37 @@ __device__ __forceinline__ void flush_row(float *__restrict__ demb, int64_t row,
     }
 }
 
+// Loads a row's current gradient slice (issued when the row starts, used when it is flushed).
+template <int NV>
+__device__ __forceinline__ void load_grad_row(const float *__restrict__ demb, int64_t row, int d4, int l,
+                                              float4 (&old)[NV]) {
+    load_row<NV>(demb, row, d4, l, old);
+}
+
+// flush_row with the row's old value already in registers: an owned row is stored as
+// old + acc (no load on the flush path), a split row is added atomically.
+template <int NV>
+__device__ __forceinline__ void flush_row_pre(float *__restrict__ demb, int64_t row, int d4, int l, float4 (&acc)[NV],
+                                              const float4 (&old)[NV], bool owned) {
+    float4 *base = reinterpret_cast<float4 *>(demb) + row * d4;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int c = l + kGroup * k;
+        if (c < d4) {
+            if (owned) {
+                base[c] = make_float4(old[k].x + acc[k].x, old[k].y + acc[k].y, old[k].z + acc[k].z, old[k].w + acc[k].w);
+            } else {
+                float *f = reinterpret_cast<float *>(base + c);
+                atomicAdd(f + 0, acc[k].x);
+                atomicAdd(f + 1, acc[k].y);
+                atomicAdd(f + 2, acc[k].z);
+                atomicAdd(f + 3, acc[k].w);
+            }
+        }
+        acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
 // Second pass of the cosine gradient: pairs in order of their second index j; each row u
 // gathers its partners e_i and adds sum_p cbar_p (e_i inv_p - c_p e_u / |e_u|^2) to demb[u].
 // pack[p] = (cbar_p, c_p, inv_p = 1 / (|e_i| |e_j|), 0), written by the first pass.
@@ -75,7 +106,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
     if (q0 >= q1) return;
     const int d4 = d >> 2;
-    float4 eu[NV], acc[NV];
+    float4 eu[NV], acc[NV], old[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float inv_nu2 = 0.f;
@@ -105,11 +136,12 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
             if (ub[t] < 0) break;
             const int64_t u = ub[t];
             if (u != cur) {
-                if (cur >= 0 && cur < n) flush_row<NV>(demb, cur, d4, l, acc, started_here);
+                if (cur >= 0 && cur < n) flush_row_pre<NV>(demb, cur, d4, l, acc, old, started_here);
                 cur = u;
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_j[q0 - 1] >> 32) != u;
                 if (u < n) {
+                    load_grad_row<NV>(demb, u, d4, l, old);
                     load_row<NV>(emb, u, d4, l, eu);
                     float a = 0.f;
 #pragma unroll
@@ -131,7 +163,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     }
     if (cur >= 0 && cur < n) {
         const bool ends_here = q1 == P || (int64_t)(order_j[q1] >> 32) != cur;
-        flush_row<NV>(demb, cur, d4, l, acc, started_here && ends_here);
+        flush_row_pre<NV>(demb, cur, d4, l, acc, old, started_here && ends_here);
     }
 }
 
@@ -155,6 +187,12 @@ inline int key_bits_for(int64_t n) {  // bits holding 0..n
 inline int64_t gate_blocks_for(int64_t P, int groups_per_cu) {
     int64_t groups = std::max<int64_t>(1, std::min<int64_t>(ceil_div(P, 4), (int64_t)device_cus() * groups_per_cu));
     return ceil_div(groups, kGateThreads / kGroup);
+}
+
+// As gate_blocks_for, but never more blocks than the chip holds at once for `kernel`: a
+// chunked kernel then runs in one round instead of leaving a tail of late groups.
+inline int64_t gate_blocks_resident(int64_t P, int groups_per_cu, const void *kernel) {
+    return std::min<int64_t>(gate_blocks_for(P, groups_per_cu), (int64_t)device_cus() * resident_blocks_per_cu(kernel));
 }
 
 }  // namespace subquad

@@ -67,37 +67,96 @@ __device__ __forceinline__ bool same_bucket(uint64_t a, uint64_t c, uint32_t n32
     return (a >> 32) == (c >> 32) && ((uint32_t)a / n32) == ((uint32_t)c / n32);
 }
 
-__global__ __launch_bounds__(256) void lsh_runs_kernel(const uint64_t *__restrict__ srec, int64_t total, int64_t n,
-                                                       uint64_t *__restrict__ runs, uint64_t *__restrict__ pcount,
-                                                       unsigned long long *__restrict__ counters) {
+constexpr int kRunsThreads = 256;
+constexpr int kRunsItems = 16;
+constexpr int kRunsTile = kRunsThreads * kRunsItems;
+
+// Length of the run starting at q (srec[q + 1] is known to be in it): the bucket's records
+// are contiguous, so gallop forward, then bisect: O(log m) loads for a run of m records.
+__device__ __forceinline__ int64_t run_length(const uint64_t *__restrict__ srec, int64_t total, int64_t q, uint32_t n32) {
+    const uint64_t me = srec[q];
+    int64_t good = q + 1, bad = total, stride = 1;
+    while (good + stride < total) {
+        if (!same_bucket(srec[good + stride], me, n32)) {
+            bad = good + stride;
+            break;
+        }
+        good += stride;
+        stride <<= 1;
+    }
+    while (bad - good > 1) {
+        const int64_t mid = good + ((bad - good) >> 1);
+        if (same_bucket(srec[mid], me, n32)) good = mid;
+        else bad = mid;
+    }
+    return bad - q;
+}
+
+// A block takes tiles of kRunsTile sorted records, kRunsItems consecutive ones per thread:
+// pass 1 counts the run starts, a block scan gives each thread its slots and one atomic per
+// block reserves them, pass 2 measures the runs and writes them (in record order).
+__global__ __launch_bounds__(kRunsThreads) void lsh_runs_kernel(const uint64_t *__restrict__ srec, int64_t total,
+                                                                int64_t n, uint64_t *__restrict__ runs,
+                                                                uint64_t *__restrict__ pcount,
+                                                                unsigned long long *__restrict__ counters) {
     const uint32_t n32 = (uint32_t)n;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q + 1 < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t me = srec[q];
-        if (q > 0 && same_bucket(srec[q - 1], me, n32)) continue;  // not a run start
-        if (!same_bucket(srec[q + 1], me, n32)) continue;          // a run of one
-        // The bucket's records are contiguous: gallop forward from q + 1, then bisect, so a
-        // run of m records costs O(log m) loads instead of m.
-        int64_t good = q + 1, bad = total, stride = 1;
-        while (good + stride < total) {
-            if (!same_bucket(srec[good + stride], me, n32)) {
-                bad = good + stride;
-                break;
-            }
-            good += stride;
-            stride <<= 1;
+    __shared__ uint32_t scan[kRunsThreads];
+    __shared__ unsigned long long base_sh, pc_sh[kRunsThreads / 64];
+    __shared__ uint64_t tile_sh[kRunsTile + 2];  // records tile-1 .. tile+kRunsTile
+    for (int64_t tile = (int64_t)blockIdx.x * kRunsTile; tile < total; tile += (int64_t)gridDim.x * kRunsTile) {
+        // coalesced staging of the tile and its two neighbours (absent ones read as ~0)
+        for (int e = threadIdx.x; e < kRunsTile + 2; e += kRunsThreads) {
+            const int64_t q = tile - 1 + e;
+            tile_sh[e] = q >= 0 && q < total ? srec[q] : ~0ull;
         }
-        while (bad - good > 1) {
-            const int64_t mid = good + ((bad - good) >> 1);
-            if (same_bucket(srec[mid], me, n32)) good = mid;
-            else bad = mid;
+        __syncthreads();
+        const int64_t q0 = tile + (int64_t)threadIdx.x * kRunsItems;
+        const uint64_t *ts = tile_sh + 1 + threadIdx.x * kRunsItems;  // ts[k] = srec[q0 + k]
+        // run starts of >= 2 records among this thread's items: bit k for item k
+        uint32_t starts = 0;
+#pragma unroll
+        for (int k = 0; k < kRunsItems; ++k) {
+            const int64_t q = q0 + k;
+            if (q + 1 >= total) break;  // the last record starts no run of two
+            const uint64_t me = ts[k];
+            const bool start = q == 0 || !same_bucket(ts[k - 1], me, n32);
+            if (start && same_bucket(ts[k + 1], me, n32)) starts |= 1u << k;
         }
-        const int64_t m = bad - q;
-        const unsigned long long r = atomicAdd(&counters[0], 1ull);
-        runs[r] = ((uint64_t)q << 32) | (uint64_t)m;
-        const uint64_t pc = (uint64_t)m * (uint64_t)(m - 1) / 2;
-        pcount[r] = pc;
-        atomicAdd(&counters[1], (unsigned long long)pc);
+        const uint32_t cnt = __builtin_popcount(starts);
+        scan[threadIdx.x] = cnt;
+        __syncthreads();
+        for (int off = 1; off < kRunsThreads; off <<= 1) {  // inclusive scan
+            const uint32_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0u;
+            __syncthreads();
+            scan[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (threadIdx.x == kRunsThreads - 1)
+            base_sh = scan[threadIdx.x] ? atomicAdd(&counters[0], (unsigned long long)scan[threadIdx.x]) : 0ull;
+        __syncthreads();
+        unsigned long long slot = base_sh + scan[threadIdx.x] - cnt;
+        unsigned long long pc = 0;
+        while (starts) {
+            const int k = __builtin_ctz(starts);
+            starts &= starts - 1;
+            const int64_t q = q0 + k;
+            const int64_t m = run_length(srec, total, q, n32);
+            runs[slot] = ((uint64_t)q << 32) | (uint64_t)m;
+            const uint64_t c = (uint64_t)m * (uint64_t)(m - 1) / 2;
+            pcount[slot] = c;
+            pc += c;
+            ++slot;
+        }
+        // one atomic per block for the pair-visit total
+        for (int off = 32; off >= 1; off >>= 1) pc += __shfl_xor(pc, off, 64);
+        if ((threadIdx.x & 63) == 0) pc_sh[threadIdx.x >> 6] = pc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kRunsThreads / 64; ++w) t += pc_sh[w];
+            if (t) atomicAdd(&counters[1], t);
+        }
+        __syncthreads();  // scan, base_sh and pc_sh are reused by the next tile
     }
 }
 
@@ -289,10 +348,11 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     uint64_t *poff = reinterpret_cast<uint64_t *>(ws + L.poff);
     unsigned long long *counters = count + 2;  // [0] runs, [1] pair visits
     const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
-    const int64_t grid = std::min<int64_t>(ceil_div(recs, emit_threads), (int64_t)device_cus() * 32);
     {
+        const int64_t grid = std::min<int64_t>(ceil_div(recs, kRunsTile), (int64_t)device_cus() * 8);
         ProfScope prof("lsh_runs_kernel", st);
-        lsh_runs_kernel<<<(unsigned)grid, 256, 0, st>>>(sorted, recs, n, runs, poff, counters);
+        lsh_runs_kernel<<<(unsigned)std::max<int64_t>(grid, 1), kRunsThreads, 0, st>>>(sorted, recs, n, runs, poff,
+                                                                                       counters);
     }
     SQ_LAUNCHED("lsh_runs_kernel");
     rc = scan_exclusive_u64(poff, recs / 2 + 1, reinterpret_cast<const uint64_t *>(counters), rscratch, st);

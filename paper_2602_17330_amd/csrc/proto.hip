@@ -215,7 +215,9 @@ __global__ void proto_fill_kernel(T *__restrict__ p, int64_t count, T v) {
 
 // ------------------------------------------------------------------ forward, Eq. (proto)
 
-// Per batch row and class split: (max logit, sum of exp(logit - max), positive logit).
+// Per batch row and class split: (max logit m, sum over the negative classes of
+// exp(logit - m), positive logit).  The positive class is kept out of the sum so that the
+// loss and 1 - softmax(positive) can be formed without cancellation.
 template <int D>
 __global__ __launch_bounds__(kProtoThreads) void proto_fwd_kernel(ProtoIn in, const float *__restrict__ P,
                                                                   const float *__restrict__ inv, int64_t tiles_per_split,
@@ -252,7 +254,8 @@ __global__ __launch_bounds__(kProtoThreads) void proto_fwd_kernel(ProtoIn in, co
             m = mt;
         }
 #pragma unroll
-        for (int v = 0; v < 16; ++v) s += expf(z[v] - m);  // exp(-inf) = 0 for missing classes
+        for (int v = 0; v < 16; ++v)  // negatives only; exp(-inf) = 0 for missing classes
+            if (c0 + acc_row(v, h) != y) s += expf(z[v] - m);
     }
     // merge the two lane halves of each column
     const float m2 = __shfl_xor(m, 32, 64), s2 = __shfl_xor(s, 32, 64), p2 = __shfl_xor(pos, 32, 64);
@@ -262,10 +265,14 @@ __global__ __launch_bounds__(kProtoThreads) void proto_fwd_kernel(ProtoIn in, co
     if (h == 0 && x < in.B) part[(int64_t)blockIdx.y * in.B + x] = make_float4(M, S, fmaxf(pos, p2), 0.f);
 }
 
-// Merges the class splits of every batch row: lse, the row's loss (0 for an excluded row)
-// and one float64 partial sum per block.
+// Merges the class splits of every batch row.  With R = sum_{c != y} exp(z_c - z_y):
+//   row loss = log(1 + R),  lse = z_y + log(1 + R),  1 - softmax_y = R / (1 + R),
+// none of which cancels when the positive class dominates (a nearly perfect prediction).
+// Writes lse and 1 - softmax_y for the backward, the row loss (0 for an excluded row) and
+// one float64 partial sum per block.
 __global__ __launch_bounds__(256) void proto_combine_kernel(ProtoIn in, const float4 *__restrict__ part, int splits,
-                                                            float *__restrict__ lse, float *__restrict__ row_loss,
+                                                            float *__restrict__ lse, float *__restrict__ omp,
+                                                            float *__restrict__ row_loss,
                                                             double *__restrict__ block_sum) {
     const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double lx = 0.0;
@@ -278,14 +285,25 @@ __global__ __launch_bounds__(256) void proto_combine_kernel(ProtoIn in, const fl
             M = fmaxf(M, p.x);
             pos = fmaxf(pos, p.z);
         }
-        float S = 0.f;
+        float Sneg = 0.f;
         for (int k = 0; k < splits; ++k) {
             const float4 p = part[(int64_t)k * in.B + x];
-            if (p.x > -INFINITY) S += p.y * expf(p.x - M);
+            if (p.x > -INFINITY) Sneg += p.y * expf(p.x - M);
         }
-        const float l = ok ? M + logf(S) : 0.f;
-        lse[x] = l;
-        const float rl = ok ? l - pos : 0.f;
+        float rl = 0.f, one_minus = 0.f;
+        if (ok) {
+            const float gap = M - pos;  // >= 0
+            if (gap < 80.f) {
+                const float R = Sneg * expf(gap);
+                rl = log1pf(R);
+                one_minus = R / (1.f + R);
+            } else {  // the positive class is negligible: R overflows, softmax_y ~ e^-gap
+                rl = gap + logf(Sneg);
+                one_minus = 1.f;
+            }
+        }
+        lse[x] = ok ? pos + rl : 0.f;
+        omp[x] = one_minus;
         if (row_loss) row_loss[x] = rl;
         lx = (double)rl;
     }
@@ -314,11 +332,12 @@ __global__ void proto_loss_final_kernel(const double *__restrict__ block_sum, in
 
 // ------------------------------------------------------------------ backward
 
-// G[c][x] = (softmax_c(x) - [c = y(x)]) * grad / tau from a recomputed Z^T tile entry.
-__device__ __forceinline__ float grad_logit(float zdot, float inv_tau, float lse_x, bool valid, bool positive, float gs) {
-    float g = valid ? expf(zdot * inv_tau - lse_x) : 0.f;
-    if (positive) g -= 1.f;
-    return g * gs;
+// G[c][x] = (softmax_c(x) - [c = y(x)]) * grad / tau from a recomputed Z^T tile entry; for
+// the positive class the stored 1 - softmax_y (no cancellation).
+__device__ __forceinline__ float grad_logit(float zdot, float inv_tau, float lse_x, float omp_x, bool valid,
+                                           bool positive, float gs) {
+    if (positive) return -omp_x * gs;
+    return valid ? expf(zdot * inv_tau - lse_x) * gs : 0.f;
 }
 
 // Batch-row side: dE[batch[x]] += sum_c G[c][x] p_c.  Fixed operand: the block's 128 batch
@@ -327,6 +346,7 @@ template <int D>
 __global__ __launch_bounds__(kProtoThreads) void proto_bwd_rows_kernel(ProtoIn in, const float *__restrict__ P,
                                                                        const float *__restrict__ inv,
                                                                        const float *__restrict__ lse,
+                                                                       const float *__restrict__ omp,
                                                                        const float *__restrict__ grad_loss,
                                                                        int64_t tiles_per_split, float *__restrict__ demb) {
     constexpr int LD = D + 4;
@@ -338,7 +358,7 @@ __global__ __launch_bounds__(kProtoThreads) void proto_bwd_rows_kernel(ProtoIn i
     const int64_t row = batch_row(in, x, y);
     float r[D / 2];
     load_fixed<D>(in.emb, row, h, r);
-    const float lse_x = row >= 0 ? lse[x] : 0.f;
+    const float lse_x = row >= 0 ? lse[x] : 0.f, omp_x = row >= 0 ? omp[x] : 0.f;
     const float gs = (grad_loss ? grad_loss[0] : 1.f) * in.inv_tau;
     f32x16 out[D / 32];
 #pragma unroll
@@ -355,7 +375,7 @@ __global__ __launch_bounds__(kProtoThreads) void proto_bwd_rows_kernel(ProtoIn i
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = acc_row(v, h);
-            g[v] = grad_logit(g[v], in.inv_tau, lse_x, row >= 0 && tvalid[i] > 0.f, c0 + i == y, gs);
+            g[v] = grad_logit(g[v], in.inv_tau, lse_x, omp_x, row >= 0 && tvalid[i] > 0.f, c0 + i == y, gs);
         }
         tile_product_t<D>(tile, g, j, h, out);
     }
@@ -374,12 +394,13 @@ template <int D>
 __global__ __launch_bounds__(kProtoThreads) void proto_bwd_protos_kernel(ProtoIn in, const float *__restrict__ P,
                                                                          const float *__restrict__ inv,
                                                                          const float *__restrict__ lse,
+                                                                         const float *__restrict__ omp,
                                                                          const float *__restrict__ grad_loss,
                                                                          int64_t tiles_per_split, bool atomic,
                                                                          float *__restrict__ dP) {
     constexpr int LD = D + 4;
     __shared__ __align__(16) float tile[32 * LD];
-    __shared__ float tlse[32];
+    __shared__ float tlse[32], tomp[32];
     __shared__ int32_t tlab[32];
     __shared__ int64_t trow[32];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, h = lane >> 5, j = lane & 31;
@@ -402,6 +423,7 @@ __global__ __launch_bounds__(kProtoThreads) void proto_bwd_protos_kernel(ProtoIn
             trow[threadIdx.x] = rr;
             tlab[threadIdx.x] = rr >= 0 ? y : -1;
             tlse[threadIdx.x] = rr >= 0 ? lse[x0 + threadIdx.x] : 0.f;
+            tomp[threadIdx.x] = rr >= 0 ? omp[x0 + threadIdx.x] : 0.f;
         }
         __syncthreads();
         stage_tile<D>(tile, in.emb, [&](int i) { return trow[i]; });
@@ -410,7 +432,7 @@ __global__ __launch_bounds__(kProtoThreads) void proto_bwd_protos_kernel(ProtoIn
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int i = acc_row(v, h);
-            g[v] = grad_logit(g[v], in.inv_tau, tlse[i], cvalid && tlab[i] >= 0, tlab[i] == c, gs);
+            g[v] = grad_logit(g[v], in.inv_tau, tlse[i], tomp[i], cvalid && tlab[i] >= 0, tlab[i] == c, gs);
         }
         tile_product_t<D>(tile, g, j, h, out);
     }
@@ -451,7 +473,7 @@ __global__ void proto_route_kernel(const int32_t *__restrict__ labels, int64_t n
 // ------------------------------------------------------------------ host side
 
 struct ProtoLayout {
-    size_t ra, rb, radix, psum, P, count, inv, part, lse, bsum, dP, total;
+    size_t ra, rb, radix, psum, P, count, inv, part, lse, omp, bsum, dP, total;
 };
 
 static ProtoLayout proto_layout(int64_t n, int32_t d, int64_t C, int64_t B) {
@@ -468,6 +490,7 @@ static ProtoLayout proto_layout(int64_t n, int32_t d, int64_t C, int64_t B) {
     L.inv = take(sizeof(float) * C);
     L.part = take(sizeof(float4) * kMaxSplits * B);
     L.lse = take(sizeof(float) * B);
+    L.omp = take(sizeof(float) * B);
     L.bsum = take(sizeof(double) * ceil_div(std::max<int64_t>(B, 1), 256));
     L.dP = take(sizeof(float) * C * d);
     L.total = off;
@@ -543,7 +566,7 @@ static int proto_fwd_d(const ProtoIn &in, char *w, const ProtoLayout &L, double 
         }
         SQ_LAUNCHED("proto_fwd_kernel");
         proto_combine_kernel<<<(unsigned)nb, 256, 0, st>>>(in, part, (int)splits, reinterpret_cast<float *>(w + L.lse),
-                                                           row_loss, bsum);
+                                                           reinterpret_cast<float *>(w + L.omp), row_loss, bsum);
         SQ_LAUNCHED("proto_combine_kernel");
     } else {
         proto_fill_kernel<double><<<1, 256, 0, st>>>(bsum, 1, 0.0);
@@ -559,14 +582,14 @@ static int proto_bwd_d(const ProtoIn &in, char *w, const ProtoLayout &L, const f
                        float *demb, hipStream_t st) {
     if (in.B == 0) return SUBQUAD_OK;
     const float *P = reinterpret_cast<const float *>(w + L.P), *inv = reinterpret_cast<const float *>(w + L.inv);
-    const float *lse = reinterpret_cast<const float *>(w + L.lse);
+    const float *lse = reinterpret_cast<const float *>(w + L.lse), *omp = reinterpret_cast<const float *>(w + L.omp);
     {
         const int64_t bx = ceil_div(in.B, kProtoRows);
         int64_t splits, tps;
         plan_splits(bx, ceil_div(in.C, 32), splits, tps);
         ProfScope prof("proto_bwd_rows_kernel", st);
-        proto_bwd_rows_kernel<D><<<dim3((unsigned)bx, (unsigned)splits), kProtoThreads, 0, st>>>(in, P, inv, lse, grad_loss,
-                                                                                                 tps, demb);
+        proto_bwd_rows_kernel<D><<<dim3((unsigned)bx, (unsigned)splits), kProtoThreads, 0, st>>>(in, P, inv, lse, omp,
+                                                                                                 grad_loss, tps, demb);
     }
     SQ_LAUNCHED("proto_bwd_rows_kernel");
     if (!through) return SUBQUAD_OK;
@@ -581,7 +604,7 @@ static int proto_bwd_d(const ProtoIn &in, char *w, const ProtoLayout &L, const f
         }
         ProfScope prof("proto_bwd_protos_kernel", st);
         proto_bwd_protos_kernel<D><<<dim3((unsigned)bx, (unsigned)splits), kProtoThreads, 0, st>>>(
-            in, P, inv, lse, grad_loss, tps, splits > 1, dP);
+            in, P, inv, lse, omp, grad_loss, tps, splits > 1, dP);
     }
     SQ_LAUNCHED("proto_bwd_protos_kernel");
     if (in.n > 0) {
