@@ -373,7 +373,9 @@ def main():
         "lsh_keys_kernel": ("hbm", n * b * r * 8 + recs * 8 + recs),
         "sort_records_scatter": ("hbm", 2 * recs * 8),
         "sort_records_hist": ("hbm", recs * 8),
-        "lsh_emit_kernel": ("hbm", recs * 8 + 8 * P),
+        # emission: every record read once, every pair key written once (short runs; the
+        # long runs' remainder has no separate figure)
+        "lsh_emit_small_kernel": ("hbm", recs * 8 + 8 * P),
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),
         "gate_fwd_kernel": ("hbm", P * (2 * d * 4 + 16)),

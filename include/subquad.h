@@ -276,6 +276,22 @@ int subquad_graph_topk(const int32_t *pairs, const float *w, int64_t P, int64_t 
                        float *vals, int64_t cap, int64_t *nnz, void *stream);
 
 /*
+ * subquad_contrastive_grad -- the training signal of the gate: margin contrastive loss in
+ * similarity form (Hadsell, Chopra and LeCun, 2006) on pair labels y_p = [label[i] = label[j]]:
+ *   loss = (1/P) sum_p  y_p (1 - f_p)^2 + (1 - y_p) max(0, f_p - margin)^2,
+ *   grad[p] = d loss / d f_p.
+ * (The paper trains with a prototype-level loss, Eq. (proto); this per-pair form gives the
+ * gate backward an upstream gradient.)  fused [P] f32, pairs [P][2] i32, label [n] i32
+ * (device); grad [P] f32 (out); loss [1] f64 (device out, may be NULL), summed in a fixed
+ * order.  Pairs with an index outside [0, n) get grad 0 and add 0.
+ *   ws / ws_bytes: subquad_contrastive_workspace_bytes() bytes, 8-byte aligned.
+ */
+size_t subquad_contrastive_workspace_bytes(void);
+int subquad_contrastive_grad(const float *fused, const int32_t *pairs, int64_t P, const int32_t *label,
+                             int64_t n, float margin, float *grad, double *loss, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/*
  * Prototype-contrastive loss (Sec. 3, prototype-contrastive consolidation; Eq. (pc), (proto)):
  *   p_c = mean of the rows of emb with label c (S_c);
  *   loss = sum over x in the batch of  log sum_{c : S_c non-empty} exp(<e_x, p_c> / tau)

@@ -50,6 +50,9 @@ SIGNATURES = {
     "subquad_graph_workspace_bytes": (c_sz, [c_i64, c_i64]),
     "subquad_graph_topk": (ctypes.c_int, [c_p, c_p, c_i64, c_i64, ctypes.c_float, c_i32, c_p, c_sz, c_p, c_p,
                                           c_p, c_i64, c_p, c_p]),
+    "subquad_contrastive_workspace_bytes": (c_sz, []),
+    "subquad_contrastive_grad": (ctypes.c_int, [c_p, c_p, c_i64, c_p, c_i64, ctypes.c_float, c_p, c_p, c_p, c_sz,
+                                                c_p]),
     "subquad_proto_workspace_bytes": (c_sz, [c_i64, c_i32, c_i64, c_i64]),
     "subquad_proto_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i64, ctypes.c_float, c_p, c_p,
                                          c_p, c_p, c_sz, c_p]),

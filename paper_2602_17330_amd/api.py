@@ -227,6 +227,25 @@ class GateFn(torch.autograd.Function):
         return demb, dW1, db1, dw2, db2, None, None, None, None, None
 
 
+CONTRASTIVE_MARGIN = 0.5
+
+
+def contrastive_grad(fused, pairs, labels, margin: float = CONTRASTIVE_MARGIN, grad=None, loss=None, ws=None):
+    """(grad [P] f32, loss [1] f64) of the per-pair margin contrastive loss on same-label pairs."""
+    fused = _dev(fused, torch.float32, "fused")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    labels = _dev(labels, torch.int32, "labels")
+    P = pairs.shape[0]
+    grad = torch.empty(P, dtype=torch.float32, device=fused.device) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float64, device=fused.device) if loss is None else loss
+    need = int(lib().subquad_contrastive_workspace_bytes())
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=fused.device)
+    check(lib().subquad_contrastive_grad(_ptr(fused), _ptr(pairs), P, _ptr(labels), labels.shape[0], margin,
+                                         _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(), _stream()))
+    return grad, loss
+
+
 def graph_topk(pairs: torch.Tensor, w: torch.Tensor, n: int, tau: float = 0.7, k: int = 0):
     """CSR similarity graph: (row_offsets int64[n+1], cols int32[nnz], vals float32[nnz])."""
     pairs = _dev(pairs, torch.int32, "pairs")

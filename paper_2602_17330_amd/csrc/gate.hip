@@ -476,6 +476,65 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws
     return radix_sort_u64(rc, rd, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, order_j, "sort_gate_j");
 }
 
+
+// ------------------------------------------------------------------ training signal
+
+constexpr int kLossThreads = 256;
+
+// Margin contrastive loss in similarity form on same-label pairs: per pair
+// y (1 - f)^2 + (1 - y) max(0, f - margin)^2 with y = [label_i = label_j], averaged over P;
+// grad[p] = its derivative by f_p.  One float64 partial per block (fixed order).
+__global__ __launch_bounds__(kLossThreads) void contrastive_kernel(const float *__restrict__ fused,
+                                                                   const int32_t *__restrict__ pairs, int64_t P,
+                                                                   const int32_t *__restrict__ label, int64_t n,
+                                                                   float margin, float *__restrict__ grad,
+                                                                   double *__restrict__ partial) {
+    const float invP = 1.f / (float)(P > 0 ? P : 1);
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * kLossThreads + threadIdx.x; p < P; p += (int64_t)gridDim.x * kLossThreads) {
+        const int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        const bool ok = i >= 0 && j >= 0 && i < n && j < n;
+        const float f = fused[p];
+        float g = 0.f, l = 0.f;
+        if (ok) {
+            if (label[i] == label[j]) {
+                const float e = 1.f - f;
+                l = e * e;
+                g = -2.f * e;
+            } else {
+                const float h = fmaxf(f - margin, 0.f);
+                l = h * h;
+                g = 2.f * h;
+            }
+        }
+        grad[p] = g * invP;
+        acc += (double)l;
+    }
+    __shared__ double red[kLossThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void contrastive_final_kernel(const double *__restrict__ partial, int nb, int64_t P, double *__restrict__ loss) {
+    __shared__ double red[kLossThreads];
+    double a = 0.0;
+    for (int k = threadIdx.x; k < nb; k += kLossThreads) a += partial[k];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = kLossThreads / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (double)(P > 0 ? P : 1);
+}
+
+static int contrastive_blocks() { return device_cus() * 4; }
+
 }  // namespace subquad
 
 using namespace subquad;
@@ -541,5 +600,30 @@ extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const in
     if (rc != SUBQUAD_OK) return rc;
     gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, H, dW1, db1, dw2, db2);
     SQ_LAUNCHED("gate_ws_finish_kernel");
+    return SUBQUAD_OK;
+}
+
+extern "C" size_t subquad_contrastive_workspace_bytes(void) { return sizeof(double) * (size_t)contrastive_blocks(); }
+
+extern "C" int subquad_contrastive_grad(const float *fused, const int32_t *pairs, int64_t P, const int32_t *label,
+                                        int64_t n, float margin, float *grad, double *loss, void *ws, size_t ws_bytes,
+                                        void *stream) {
+    clear_error();
+    SQ_REQUIRE(P >= 0 && n >= 0, SUBQUAD_ERR_ARG, "P and n must be >= 0");
+    SQ_REQUIRE(P == 0 || (fused && pairs && label && grad), SUBQUAD_ERR_ARG, "null pointer argument");
+    SQ_REQUIRE(margin == margin, SUBQUAD_ERR_ARG, "margin is NaN");
+    const int nb = contrastive_blocks();
+    SQ_REQUIRE(ws && ws_bytes >= sizeof(double) * (size_t)nb, SUBQUAD_ERR_WORKSPACE,
+               "contrastive workspace of %zu bytes, %zu needed", ws_bytes, sizeof(double) * (size_t)nb);
+    SQ_REQUIRE(((uintptr_t)ws & 7) == 0, SUBQUAD_ERR_ARG, "workspace must be 8-byte aligned");
+    if (P == 0 && !loss) return SUBQUAD_OK;
+    hipStream_t st = as_stream(stream);
+    double *partial = static_cast<double *>(ws);
+    contrastive_kernel<<<(unsigned)nb, kLossThreads, 0, st>>>(fused, pairs, P, label, n, margin, grad, partial);
+    SQ_LAUNCHED("contrastive_kernel");
+    if (loss) {
+        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(partial, nb, P, loss);
+        SQ_LAUNCHED("contrastive_final_kernel");
+    }
     return SUBQUAD_OK;
 }

@@ -70,6 +70,7 @@ __device__ __forceinline__ bool same_bucket(uint64_t a, uint64_t c, uint32_t n32
 constexpr int kRunsThreads = 256;
 constexpr int kRunsItems = 16;
 constexpr int kRunsTile = kRunsThreads * kRunsItems;
+constexpr int kSmallRun = 8;  // runs up to this many records: all their pairs in one thread
 
 // Length of the run starting at q (srec[q + 1] is known to be in it): the bucket's records
 // are contiguous, so gallop forward, then bisect: O(log m) loads for a run of m records.
@@ -94,14 +95,18 @@ __device__ __forceinline__ int64_t run_length(const uint64_t *__restrict__ srec,
 
 // A block takes tiles of kRunsTile sorted records, kRunsItems consecutive ones per thread:
 // pass 1 counts the run starts, a block scan gives each thread its slots and one atomic per
-// block reserves them, pass 2 measures the runs and writes them (in record order).
+// block reserves them, pass 2 measures the runs.  Runs of at most kSmallRun records go to
+// `runs` (in record order: one thread will walk all their pairs); longer ones, few, go to
+// `bruns` with their pair counts in `bpcount` (their pairs are spread over threads).
+// counters: [0] small runs, [1] pairs of the long runs, [2] long runs.
 __global__ __launch_bounds__(kRunsThreads) void lsh_runs_kernel(const uint64_t *__restrict__ srec, int64_t total,
                                                                 int64_t n, uint64_t *__restrict__ runs,
-                                                                uint64_t *__restrict__ pcount,
+                                                                uint64_t *__restrict__ bruns,
+                                                                uint64_t *__restrict__ bpcount,
                                                                 unsigned long long *__restrict__ counters) {
     const uint32_t n32 = (uint32_t)n;
     __shared__ uint32_t scan[kRunsThreads];
-    __shared__ unsigned long long base_sh, pc_sh[kRunsThreads / 64];
+    __shared__ unsigned long long base_sh;
     __shared__ uint64_t tile_sh[kRunsTile + 2];  // records tile-1 .. tile+kRunsTile
     for (int64_t tile = (int64_t)blockIdx.x * kRunsTile; tile < total; tile += (int64_t)gridDim.x * kRunsTile) {
         // coalesced staging of the tile and its two neighbours (absent ones read as ~0)
@@ -135,28 +140,25 @@ __global__ __launch_bounds__(kRunsThreads) void lsh_runs_kernel(const uint64_t *
             base_sh = scan[threadIdx.x] ? atomicAdd(&counters[0], (unsigned long long)scan[threadIdx.x]) : 0ull;
         __syncthreads();
         unsigned long long slot = base_sh + scan[threadIdx.x] - cnt;
-        unsigned long long pc = 0;
         while (starts) {
             const int k = __builtin_ctz(starts);
             starts &= starts - 1;
             const int64_t q = q0 + k;
             const int64_t m = run_length(srec, total, q, n32);
-            runs[slot] = ((uint64_t)q << 32) | (uint64_t)m;
-            const uint64_t c = (uint64_t)m * (uint64_t)(m - 1) / 2;
-            pcount[slot] = c;
-            pc += c;
+            const uint64_t rec = ((uint64_t)q << 32) | (uint64_t)m;
+            if (m <= kSmallRun) {
+                runs[slot] = rec;
+            } else {  // a long run: rare, one atomic each
+                runs[slot] = 0;  // an empty small run (m = 0) keeps the slot list dense
+                const unsigned long long b = atomicAdd(&counters[2], 1ull);
+                bruns[b] = rec;
+                const uint64_t c = (uint64_t)m * (uint64_t)(m - 1) / 2;
+                bpcount[b] = c;
+                atomicAdd(&counters[1], (unsigned long long)c);
+            }
             ++slot;
         }
-        // one atomic per block for the pair-visit total
-        for (int off = 32; off >= 1; off >>= 1) pc += __shfl_xor(pc, off, 64);
-        if ((threadIdx.x & 63) == 0) pc_sh[threadIdx.x >> 6] = pc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long t = 0;
-            for (int w = 0; w < kRunsThreads / 64; ++w) t += pc_sh[w];
-            if (t) atomicAdd(&counters[1], t);
-        }
-        __syncthreads();  // scan, base_sh and pc_sh are reused by the next tile
+        __syncthreads();  // scan and base_sh are reused by the next tile
     }
 }
 
@@ -195,46 +197,132 @@ __device__ __forceinline__ bool earlier_band(const uint64_t *__restrict__ sig, i
     return false;
 }
 
-// Step 3b.  One thread per (run, x < y) pair of records, all runs flattened by the prefix
-// sum of their pair counts; k-th pair of a run: y = the largest y with y(y-1)/2 <= k,
-// x = k - y(y-1)/2.
+// Whether records la < lb of one bucket (band beta) make a candidate pair first found in
+// this band: same repertoire, equal tuples, no earlier band with equal tuples.
+__device__ __forceinline__ bool pair_found_here(uint32_t la, uint32_t lb, uint32_t n32, const uint64_t *__restrict__ sig,
+                                                int32_t M, int32_t b, int32_t r, const uint8_t *__restrict__ F,
+                                                const int64_t *__restrict__ offs, int64_t R, int64_t &i, int64_t &j) {
+    const int beta = (int)(la / n32);
+    if (beta >= b) return false;
+    i = (int64_t)(la - (uint32_t)beta * n32);
+    j = (int64_t)(lb - (uint32_t)beta * n32);  // i < j within a run
+    if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) return false;
+    if (!tuple_equal(sig, M, i, j, beta, r)) return false;
+    return !earlier_band(sig, M, F, b, r, i, j, beta);
+}
+
+// Slots in the pair-key list for the threads of a block that want one: an LDS counter
+// hands out block-local ranks, then one global atomic per block reserves them.  Every
+// thread of the block must call it (it synchronises the block).
+__device__ __forceinline__ unsigned long long block_slot(unsigned long long *count, bool want, uint32_t *lcount,
+                                                         unsigned long long *gbase) {
+    if (threadIdx.x == 0) *lcount = 0u;
+    __syncthreads();
+    const uint32_t local = want ? atomicAdd(lcount, 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) *gbase = *lcount ? atomicAdd(count, (unsigned long long)*lcount) : 0ull;
+    __syncthreads();
+    return *gbase + local;
+}
+
+constexpr int kEmitThreads = 256;
+
+// Step 3b, short runs (<= kSmallRun records): a block takes 256 runs, scans their pair
+// counts in LDS, and its threads walk the block's pairs in rounds of 256 (a pair finds its
+// run by bisection in LDS; k-th pair of a run: y = the largest y with y(y-1)/2 <= k,
+// x = k - y(y-1)/2).
+__global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
+    const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
+    const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+    const uint64_t *__restrict__ runs, const unsigned long long *__restrict__ counters, uint64_t *__restrict__ pkeys,
+    int64_t cap, unsigned long long *__restrict__ count) {
+    __shared__ uint32_t vend[kEmitThreads];  // inclusive prefix of the runs' pair counts
+    __shared__ uint64_t rsh[kEmitThreads];
+    __shared__ uint32_t lcount;
+    __shared__ unsigned long long gbase;
+    const int64_t nruns = (int64_t)counters[0];
+    const uint32_t n32 = (uint32_t)n;
+    for (int64_t tile = (int64_t)blockIdx.x * kEmitThreads; tile < nruns; tile += (int64_t)gridDim.x * kEmitThreads) {
+        const int64_t t = tile + threadIdx.x;
+        const uint64_t run = t < nruns ? runs[t] : 0ull;
+        const uint32_t m = (uint32_t)run;  // 0 for a slot whose run is long
+        rsh[threadIdx.x] = run;
+        vend[threadIdx.x] = m * (m - (m > 0)) / 2;
+        __syncthreads();
+        for (int off = 1; off < kEmitThreads; off <<= 1) {
+            const uint32_t v = threadIdx.x >= off ? vend[threadIdx.x - off] : 0u;
+            __syncthreads();
+            vend[threadIdx.x] += v;
+            __syncthreads();
+        }
+        const uint32_t V = vend[kEmitThreads - 1];
+        for (uint32_t v0 = 0; v0 < V; v0 += kEmitThreads) {
+            const uint32_t v = v0 + threadIdx.x;
+            bool want = false;
+            int64_t i = 0, j = 0;
+            if (v < V) {
+                int lo = 0, hi = kEmitThreads - 1;  // first run with vend > v
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (vend[mid] > v) hi = mid; else lo = mid + 1;
+                }
+                const uint32_t k = v - (lo ? vend[lo - 1] : 0u);
+                uint32_t y = 1;
+                while ((y + 1) * y / 2 <= k) ++y;  // y < kSmallRun
+                const uint32_t x = k - y * (y - 1) / 2;
+                const int64_t start = (int64_t)(rsh[lo] >> 32);
+                want = pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs,
+                                       R, i, j);
+            }
+            const unsigned long long slot = block_slot(count, want, &lcount, &gbase);
+            if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+        }
+        __syncthreads();  // vend and rsh are reused by the next tile
+    }
+}
+
+// Step 3b, long runs: one thread per (run, x < y) pair of records, the long runs' pairs
+// flattened by the prefix sum of their pair counts; k-th pair of a run: y = the largest y
+// with y(y-1)/2 <= k, x = k - y(y-1)/2.
 __global__ __launch_bounds__(1024) void lsh_emit_kernel(
     const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
     const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
     const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
-    const int64_t nruns = (int64_t)counters[0];
+    __shared__ uint32_t lcount;
+    __shared__ unsigned long long gbase;
+    const int64_t nruns = (int64_t)counters[2];
     const uint64_t visits = (uint64_t)counters[1];
     const uint32_t n32 = (uint32_t)n;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < visits;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        int64_t lo = 0, hi = nruns - 1;  // last run with poff <= t
-        while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (poff[mid] <= t) lo = mid; else hi = mid - 1;
+    // block-uniform trip count: every thread reaches block_slot in every round
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < visits; base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t t = base + threadIdx.x;
+        bool want = false;
+        int64_t i = 0, j = 0;
+        if (t < visits) {
+            int64_t lo = 0, hi = nruns - 1;  // last run with poff <= t
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (poff[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const uint64_t run = runs[lo];
+            const uint64_t start = run >> 32;
+            const uint64_t k = t - poff[lo];
+            uint64_t y = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+            while (y * (y - 1) / 2 > k) --y;
+            while ((y + 1) * y / 2 <= k) ++y;
+            const uint64_t x = k - y * (y - 1) / 2;
+            want = pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs, R,
+                                   i, j);
         }
-        const uint64_t run = runs[lo];
-        const uint64_t start = run >> 32;
-        const uint64_t k = t - poff[lo];
-        uint64_t y = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
-        while (y * (y - 1) / 2 > k) --y;
-        while ((y + 1) * y / 2 <= k) ++y;
-        const uint64_t x = k - y * (y - 1) / 2;
-        const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
-        const int beta = (int)(la / n32);
-        if (beta >= b) continue;
-        const int64_t i = (int64_t)(la - (uint32_t)beta * n32);
-        const int64_t j = (int64_t)(lb - (uint32_t)beta * n32);  // i < j within a run
-        if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) continue;
-        if (!tuple_equal(sig, M, i, j, beta, r)) continue;
-        if (earlier_band(sig, M, F, b, r, i, j, beta)) continue;
-        const unsigned long long slot = atomicAdd(count, 1ull);
-        if ((int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+        const unsigned long long slot = block_slot(count, want, &lcount, &gbase);
+        if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
     }
 }
 
 __global__ void lsh_init_kernel(unsigned long long *count) {
-    if (blockIdx.x == 0 && threadIdx.x < 4) count[threadIdx.x] = 0ull;  // pairs, runs, visits, spare
+    // [0] pairs, [1] spare, [2] short runs, [3] long-run pairs, [4] long runs, [5] spare
+    if (blockIdx.x == 0 && threadIdx.x < 6) count[threadIdx.x] = 0ull;
 }
 
 // Publishes P, the capacity status, and the clamped pair count used by the pair sort.
@@ -345,22 +433,33 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted, "sort_records");
     if (rc != SUBQUAD_OK) return rc;
     uint64_t *runs = reinterpret_cast<uint64_t *>(ws + L.runs);
-    uint64_t *poff = reinterpret_cast<uint64_t *>(ws + L.poff);
-    unsigned long long *counters = count + 2;  // [0] runs, [1] pair visits
-    const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
+    // the long runs (>= kSmallRun + 1 records each, so at most recs / 9 / 2 of them) and
+    // their pair counts share the poff region
+    const int64_t big_cap = recs / (2 * (kSmallRun + 1)) + 1;
+    uint64_t *bruns = reinterpret_cast<uint64_t *>(ws + L.poff);
+    uint64_t *bpoff = bruns + big_cap;
+    unsigned long long *counters = count + 2;  // [0] short runs, [1] long-run pairs, [2] long runs
     {
         const int64_t grid = std::min<int64_t>(ceil_div(recs, kRunsTile), (int64_t)device_cus() * 8);
         ProfScope prof("lsh_runs_kernel", st);
-        lsh_runs_kernel<<<(unsigned)std::max<int64_t>(grid, 1), kRunsThreads, 0, st>>>(sorted, recs, n, runs, poff,
-                                                                                       counters);
+        lsh_runs_kernel<<<(unsigned)std::max<int64_t>(grid, 1), kRunsThreads, 0, st>>>(sorted, recs, n, runs, bruns,
+                                                                                       bpoff, counters);
     }
     SQ_LAUNCHED("lsh_runs_kernel");
-    rc = scan_exclusive_u64(poff, recs / 2 + 1, reinterpret_cast<const uint64_t *>(counters), rscratch, st);
+    {
+        ProfScope prof("lsh_emit_small_kernel", st);
+        lsh_emit_small_kernel<<<(unsigned)((int64_t)device_cus() * 8), kEmitThreads, 0, st>>>(
+            sorted, n, sig, M, b, r, F, offs, R, nb, runs, counters, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap,
+            count);
+    }
+    SQ_LAUNCHED("lsh_emit_small_kernel");
+    rc = scan_exclusive_u64(bpoff, big_cap, reinterpret_cast<const uint64_t *>(counters + 2), rscratch, st);
     if (rc != SUBQUAD_OK) return rc;
     {
+        const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
         ProfScope prof("lsh_emit_kernel", st);
         lsh_emit_kernel<<<(unsigned)((int64_t)device_cus() * 16), emit_threads, 0, st>>>(
-            sorted, n, sig, M, b, r, F, offs, R, nb, runs, poff, counters,
+            sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff, counters,
             reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
     }
     SQ_LAUNCHED("lsh_emit_kernel");

@@ -67,6 +67,9 @@ class Pipeline:
         self.gate_ws = torch.empty(api.gate_bwd_workspace_bytes(self.W[0].shape[0], cap),
                                    dtype=torch.uint8, device=dev)
         self.grads = [torch.zeros_like(w) for w in self.W] + [torch.zeros_like(self.emb)]
+        self.grad_fused_buf = torch.empty(cap, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.loss_ws = torch.empty(int(lib().subquad_contrastive_workspace_bytes()), dtype=torch.uint8, device=dev)
 
     # ---------------------------------------------------------------- stages
     def minhash(self):
@@ -103,14 +106,11 @@ class Pipeline:
             api.gate_fwd(*self.gate_args(), out=self.fused[: self.P])
 
     def loss_grad(self):
-        """Margin contrastive loss on same-family labels (training harness, torch ops)."""
+        """Margin contrastive loss on same-family labels (the gate's training signal)."""
         P = self.P
-        pr = self.pairs[:P].long()
-        y = (self.family[pr[:, 0]] == self.family[pr[:, 1]]).float()
-        f = self.fused[:P]
-        hinge = torch.clamp(f - self.cfg.margin, min=0.0)
-        self.loss = (y * (1 - f) ** 2 + (1 - y) * hinge ** 2).sum() / max(P, 1)
-        self.grad_fused = (-2.0 * y * (1 - f) + 2.0 * (1 - y) * hinge) / max(P, 1)
+        api.contrastive_grad(self.fused[:P], self.pairs[:P], self.family, self.cfg.margin,
+                             grad=self.grad_fused_buf[:P], loss=self.loss, ws=self.loss_ws)
+        self.grad_fused = self.grad_fused_buf[:P]
 
     def gate_bwd(self):
         for g in self.grads:

@@ -129,3 +129,14 @@ def test_proto_validation(L):
     assert L.subquad_proto_fwd(*args[:-1], ctypes.c_float(0.0), FAKE, NULL, NULL, 4096, ws, NULL) == 1  # tau
     assert L.subquad_proto_fwd(*args, NULL, NULL, NULL, 4096, ws, NULL) == 1             # null loss
     assert L.subquad_proto_bwd(*args, NULL, 1, NULL, 4096, ws, NULL) == 1                # null demb
+
+
+def test_contrastive_validation(L):
+    ws = L.subquad_contrastive_workspace_bytes()
+    assert ws >= 8
+    assert L.subquad_contrastive_grad(FAKE, FAKE, 10, FAKE, 10, ctypes.c_float(0.5), FAKE, FAKE, 4096, ws - 1,
+                                      NULL) == 5
+    assert L.subquad_contrastive_grad(FAKE, NULL, 10, FAKE, 10, ctypes.c_float(0.5), FAKE, FAKE, 4096, ws,
+                                      NULL) == 1
+    assert L.subquad_contrastive_grad(FAKE, FAKE, -1, FAKE, 10, ctypes.c_float(0.5), FAKE, FAKE, 4096, ws,
+                                      NULL) == 1

@@ -218,3 +218,26 @@ def test_backward_hub_rows():
     for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
         ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
         assert ok, (name, rel)
+
+
+def test_contrastive_grad():
+    """The gate's training signal against the oracle's loss and gradient (float32 kernel, the
+    loss summed in float64), including out-of-range pairs (gradient 0) and P = 0."""
+    rep = synth.tiny(seed=12)
+    rng = np.random.default_rng(12)
+    pairs = synth.random_pairs(rep.n, 5000, 12, family=rep.family, same_frac=0.5)
+    f = rng.uniform(-1.0, 1.5, pairs.shape[0]).astype(np.float32)
+    say("contrastive loss gradient")
+    g, loss = sq.api.contrastive_grad(dev(f), dev(pairs), dev(rep.family.astype(np.int32)), 0.5)
+    torch.cuda.synchronize()
+    y = (rep.family[pairs[:, 0]] == rep.family[pairs[:, 1]]).astype(np.float64)
+    ref_l, ref_g = ogate.contrastive_loss(f.astype(np.float64), y, 0.5)
+    assert abs(loss.item() - ref_l) <= 1e-6 * abs(ref_l)
+    assert np.allclose(g.cpu().numpy(), ref_g, rtol=1e-5, atol=1e-6 * np.abs(ref_g).max())
+    bad = pairs.copy()
+    bad[:10, 1] = rep.n + 3
+    g2, _ = sq.api.contrastive_grad(dev(f), dev(bad), dev(rep.family.astype(np.int32)), 0.5)
+    assert not g2.cpu().numpy()[:10].any()
+    g0, l0 = sq.api.contrastive_grad(dev(f[:0]), dev(pairs[:0]), dev(rep.family.astype(np.int32)), 0.5)
+    torch.cuda.synchronize()
+    assert g0.shape == (0,) and l0.item() == 0.0
