@@ -33,6 +33,43 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 SW_OPS_PER_CELL = 8
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak
 
+# Source files whose text defines each kernel: measured HBM traffic (profiles/hbm_traffic.tsv,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while their hash still
+# matches the one recorded with the measurement.
+KERNEL_SOURCES = {
+    "gate_bwd_kernel": ["gate.hip", "gate_util.h"], "gate_fwd_kernel": ["gate.hip", "gate_util.h"],
+    "gate_cos_bwd_j_kernel": ["gate_util.h"], "gate_wgrad_kernel": ["gate.hip", "gate_util.h"],
+    "lsh_emit_small_kernel": ["lsh.hip"], "lsh_emit_kernel": ["lsh.hip"], "lsh_keys_kernel": ["lsh.hip"],
+    "lsh_runs_kernel": ["lsh.hip"], "minhash3_kernel": ["minhash.hip"], "align_kernel": ["align.hip"],
+    "radix_scatter_kernel": ["radix.hip"], "radix_hist_kernel": ["radix.hip"],
+    "proto_fwd_kernel": ["proto.hip"], "proto_bwd_rows_kernel": ["proto.hip"],
+    "proto_bwd_protos_kernel": ["proto.hip"],
+}
+
+
+def kernel_source_sha(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2602_17330_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """(read + written bytes per launch, detail) from profiles/hbm_traffic.tsv, or (None, reason)."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.tsv")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None, "no counter measurement for this kernel"
+    rows = [ln.split("\t") for ln in open(path).read().splitlines() if ln and not ln.startswith("#")]
+    rows = [r for r in rows if r[0] == kernel]
+    if len(rows) != 1:
+        return None, "no single counter measurement for this kernel"
+    if rows[0][4] != kernel_source_sha(kernel):
+        return None, "kernel source changed since the counters were taken"
+    rd, wr = float(rows[0][2]), float(rows[0][3])
+    return rd + wr, {"read_bytes": rd, "write_bytes": wr, "source": "profiles/pipeline_rep1m_hbm_traffic.md"}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -405,8 +442,11 @@ def main():
         kernels[name] = entry
     dominant = max((k for k in kernels if "bound" in kernels[k]), key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dominant]
+    traffic, traffic_detail = measured_traffic(dominant)
     roof = {"bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"], "unit": kd["unit"],
-            "frac": kd["frac"], "traffic": None, "kernel": dominant, "avg_launch_ms": kd["avg_launch_ms"]}
+            "frac": kd["frac"], "traffic": traffic, "traffic_detail": traffic_detail, "kernel": dominant,
+            "avg_launch_ms": kd["avg_launch_ms"],
+            "alg_bytes_per_launch": kd.get("alg_bytes_per_launch", kd.get("alg_ops_per_launch"))}
     sw_gcups = kernels.get("align_kernel", {}).get("gcups")
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
