@@ -138,7 +138,7 @@ def gate_2p20(torch, sq, steps, warmup):
     args = (E, lens, vg, self_s, pairs, align, *W)
     fused = torch.empty(pairs.shape[0], dtype=torch.float32, device="cuda")
     grads = [torch.zeros_like(w) for w in W] + [torch.zeros_like(E)]
-    ws = torch.empty(api.gate_bwd_workspace_bytes(W[0].shape[0], pairs.shape[0]), dtype=torch.uint8,
+    ws = torch.empty(api.gate_bwd_workspace_bytes(W[0].shape[0], pairs.shape[0], E.shape[0]), dtype=torch.uint8,
                      device="cuda")
     P = pairs.shape[0]
 
@@ -172,10 +172,21 @@ def gate_2p20(torch, sq, steps, warmup):
         bwd_ms.append(ev[2].elapsed_time(ev[3]))
     wall = (time.perf_counter() - t0) / steps
     f_ms, b_ms = float(np.mean(fwd_ms)), float(np.mean(bwd_ms))
+    # the fused training pass (forward + loss + backward in one pass over the pairs)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    fam32 = fam.to(torch.int32)
+
+    def train():
+        for g in grads:
+            g.zero_()
+        sq.api.gate_train(*args, fam32, 0.5, fused=fused, loss=loss, grads=tuple(grads), ws=ws)
+
+    train_s = time_region(torch, train, steps, warmup)
     return dict(pairs=P, candidates_total=int(Pall), fwd_ms=f_ms, bwd_ms=b_ms,
                 pairs_per_s_kernels=P / ((f_ms + b_ms) / 1e3),
                 pairs_per_s_step=P / wall, step_ms=wall * 1e3,
                 fwd_eff_GBs=P * 1040 / (f_ms / 1e3) / 1e9, bwd_eff_GBs=P * 2064 / (b_ms / 1e3) / 1e9,
+                train_ms=train_s * 1e3, train_pairs_per_s=P / train_s,
                 workload="2^20 pairs sampled from the candidates of the 100,000-sequence Zipf "
                          "repertoire, d=128, H=64, fp32")
 
@@ -415,10 +426,10 @@ def main():
         "lsh_emit_small_kernel": ("hbm", recs * 8 + 8 * P),
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),
-        "gate_fwd_kernel": ("hbm", P * (2 * d * 4 + 16)),
-        # backward, 2*d*4 + 16 (recompute) + 2*d*4 (dE) bytes per pair, split over its two
-        # passes: rows by i write e_i's gradient, rows by j write e_j's
-        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 16 + d * 4)),
+        # the fused gate pass: forward, loss and backward, 2*d*4 + 16 (rows and scalars) + 4 (the
+        # fused value) + 2*d*4 (dE) bytes per pair, split over its two passes: rows by i write
+        # e_i's gradient, rows by j write e_j's
+        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 20 + d * 4)),
         "gate_cos_bwd_j_kernel": ("hbm", P * d * 4),
         "sort_gate_i_scatter": ("hbm", 2 * P * 8),
         "sort_gate_j_scatter": ("hbm", 2 * P * 8),
@@ -474,7 +485,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {n} synthetic CDR3s, lengths {p['Lmin']}-{p['Lmax']}, "
                                f"M={M}, {b}x{cfg.r} bands, BLOSUM62 gaps 10/1, d={d}, H=64; step = MinHash + "
-                               f"LSH + Smith-Waterman + gate fwd + loss grad + gate bwd",
+                               f"LSH + Smith-Waterman + gate (forward, contrastive loss and backward in "
+                               f"one fused pass)",
                    "n": n, "candidates": P, "cells": cells, "parallelism": "single GPU"},
         "sw_kernel_gcups": sw_gcups,
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},

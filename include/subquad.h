@@ -95,7 +95,8 @@ int subquad_check_seqs(const uint8_t *seqs, const int32_t *lens, int64_t n, int3
  *   row i of h_t(x), with simple tabulation h_t(x) = XOR_p T[t][p][x_p] and the 20*k*M table
  *   words T taken, in the order t, p, residue, from the SplitMix64 sequence started at
  *   `seed`.  Requires k == 3 (the hot path's shingle length), 1 <= M <= 256, 3 <= stride
- *   <= 64, stride % 4 == 0.  Row lengths must lie in [k, stride] (subquad_check_seqs).
+ *   <= 64, stride % 4 == 0, seqs 4-byte aligned.  Row lengths must lie in [k, stride]
+ *   (subquad_check_seqs).
  */
 int subquad_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
                     int32_t k, int32_t M, uint64_t seed, uint64_t *sig, void *stream);
@@ -197,9 +198,9 @@ int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens
                      const float *w2, const float *b2, int32_t H, float *fused, float *gate,
                      void *stream);
 
-/* Bytes of device workspace subquad_gate_bwd needs for H hidden units and P pairs
- * (0 when H <= 0, P < 0 or P >= 2^32). */
-size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P);
+/* Bytes of device workspace subquad_gate_bwd and subquad_gate_train need for H hidden units,
+ * P pairs and n nodes (0 when H <= 0, P < 0, n < 0 or P >= 2^32). */
+size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P, int64_t n);
 
 /*
  * subquad_gate_bwd -- gradient of L = sum_p grad_fused[p] * fused[p] (the backward of
@@ -212,7 +213,7 @@ size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P);
  * worker's chunk is updated with a plain read-modify-write, a row split between chunks with
  * float32 atomics (summation order, and last bits, may then vary between runs).  demb must
  * be 16-byte aligned.
- *   ws / ws_bytes: at least subquad_gate_bwd_workspace_bytes(H, P) bytes, 256-byte aligned.
+ *   ws / ws_bytes: at least subquad_gate_bwd_workspace_bytes(H, P, n) bytes, 256-byte aligned.
  */
 int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
                      const int32_t *vgene, const int32_t *self, const int32_t *pairs,
@@ -220,6 +221,23 @@ int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens
                      const float *w2, const float *b2, int32_t H, const float *grad_fused,
                      float *dW1, float *db1, float *dw2, float *db2, float *demb, void *ws,
                      size_t ws_bytes, void *stream);
+
+/*
+ * subquad_gate_train -- one training pass of the gate: the forward of subquad_gate_fwd, the
+ * loss of subquad_contrastive_grad on label[] (margin contrastive, averaged over P) and the
+ * backward of subquad_gate_bwd with that loss's gradient, in one pass over the pairs (each
+ * pair's fused value, loss term and gradient are formed where the backward recomputes the
+ * forward, so the forward is evaluated once).  Arguments as subquad_gate_bwd, plus
+ * label [n] i32 (device) and margin; fused [P] f32 (out, may be NULL) receives the forward;
+ * loss [1] f64 (device out) the mean loss, summed in a fixed order of blocks.  Gradients
+ * ACCUMULATE as in subquad_gate_bwd.  ws: subquad_gate_bwd_workspace_bytes(H, P, n) bytes.
+ */
+int subquad_gate_train(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                       const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                       const int32_t *align, int64_t P, const float *W1, const float *b1,
+                       const float *w2, const float *b2, int32_t H, const int32_t *label,
+                       float margin, float *fused, double *loss, float *dW1, float *db1,
+                       float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * subquad_edit_batch_ws -- the paper's own affinity recurrence (Appendix F.3), a weighted

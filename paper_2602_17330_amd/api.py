@@ -181,10 +181,10 @@ def gate_fwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, return_ga
     return (fused, gate) if return_gate else fused
 
 
-def gate_bwd_workspace_bytes(H: int, P: int) -> int:
-    need = int(lib().subquad_gate_bwd_workspace_bytes(int(H), int(P)))
+def gate_bwd_workspace_bytes(H: int, P: int, n: int) -> int:
+    need = int(lib().subquad_gate_bwd_workspace_bytes(int(H), int(P), int(n)))
     if need == 0:
-        raise SubquadError(1, f"no gate workspace size for H={H}, P={P}")
+        raise SubquadError(1, f"no gate workspace size for H={H}, P={P}, n={n}")
     return need
 
 
@@ -199,7 +199,7 @@ def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fuse
         grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(w2), torch.zeros_like(b2),
                  torch.zeros_like(emb) if need_emb else None)
     dW1, db1, dw2, db2, demb = grads
-    need = gate_bwd_workspace_bytes(H, pairs.shape[0])
+    need = gate_bwd_workspace_bytes(H, pairs.shape[0], emb.shape[0])
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
     check(lib().subquad_gate_bwd(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene),
@@ -207,6 +207,29 @@ def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fuse
                                  _ptr(b1), _ptr(w2), _ptr(b2), H, _ptr(gf), _ptr(dW1), _ptr(db1),
                                  _ptr(dw2), _ptr(db2), _ptr(demb), _ptr(ws), ws.numel(), _stream()))
     return dW1, db1, dw2, db2, demb
+
+
+def gate_train(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, labels, margin: float = 0.5,
+               fused=None, loss=None, grads=None, ws: torch.Tensor | None = None):
+    """Fused forward + contrastive loss + backward.  Returns (fused, loss, (dW1, db1, dw2, db2, demb));
+    gradients accumulate into ``grads`` when given."""
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = _gate_args(
+        emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
+    labels = _dev(labels, torch.int32, "labels")
+    H, P = W1.shape[0], pairs.shape[0]
+    fused = torch.empty(P, dtype=torch.float32, device=emb.device) if fused is None else fused
+    loss = torch.empty(1, dtype=torch.float64, device=emb.device) if loss is None else loss
+    if grads is None:
+        grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(w2), torch.zeros_like(b2),
+                 torch.zeros_like(emb))
+    need = gate_bwd_workspace_bytes(H, P, emb.shape[0])
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
+    check(lib().subquad_gate_train(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s),
+                                   _ptr(pairs), _ptr(align_s), P, _ptr(W1), _ptr(b1), _ptr(w2), _ptr(b2), H,
+                                   _ptr(labels), margin, _ptr(fused), _ptr(loss), *[_ptr(g) for g in grads],
+                                   _ptr(ws), ws.numel(), _stream()))
+    return fused, loss, grads
 
 
 class GateFn(torch.autograd.Function):

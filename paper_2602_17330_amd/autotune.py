@@ -71,7 +71,7 @@ def tune(pipe, reps: int = 3, cache_path: str | None = None, knobs=None) -> dict
         "minhash": pipe.minhash,
         "lsh": pipe.lsh,
         "align": pipe.align,
-        "gate": lambda: (pipe.gate_fwd(), pipe.loss_grad(), pipe.gate_bwd()),
+        "gate": pipe.gate,
     }
     best, timings = {}, {}
     for name in knobs or CANDIDATES:

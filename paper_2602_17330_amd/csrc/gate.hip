@@ -30,13 +30,25 @@ struct GateIn {
     int64_t P;
     const float *W1, *b1, *w2, *b2;
     int32_t H;
+    // (self score, length, V-gene, label) per node, one 16-byte record: a partner costs one
+    // gather instead of four.  NULL: the separate arrays above are read.
+    const int4 *node;
 };
+
+// node[k] = (self[k], lens[k], vgene[k], label ? label[k] : 0).
+__global__ void gate_node_pack_kernel(const int32_t *__restrict__ self, const int32_t *__restrict__ lens,
+                                      const int32_t *__restrict__ vgene, const int32_t *__restrict__ label, int64_t n,
+                                      int4 *__restrict__ node) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        node[k] = make_int4(self[k], lens[k], vgene[k], label ? label[k] : 0);
+}
 
 // One pair's inputs as loaded by a group: the rows, the integer features and e_j.
 template <int NV>
 struct PairLoad {
     int64_t p, i, j;  // i < 0: no pair (past the chunk, or out of range)
     float s, x2, x3;
+    bool same_label;  // packed records only
     float4 ej[NV];
 };
 
@@ -48,10 +60,19 @@ __device__ __forceinline__ void load_pair(const GateIn &in, int64_t p, int64_t i
     pl.i = ok ? i : -1;
     pl.j = ok ? j : -1;
     if (!ok) return;
-    const float si = (float)in.self[i], sj = (float)in.self[j];
-    pl.s = (float)in.align[p] / sqrtf(si * sj);
-    pl.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
-    pl.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
+    if (in.node) {
+        const int4 a = in.node[i], b = in.node[j];
+        pl.s = (float)in.align[p] / sqrtf((float)a.x * (float)b.x);
+        pl.x2 = fabsf((float)(a.y - b.y));
+        pl.x3 = a.z == b.z ? 1.f : 0.f;
+        pl.same_label = a.w == b.w;
+    } else {
+        const float si = (float)in.self[i], sj = (float)in.self[j];
+        pl.s = (float)in.align[p] / sqrtf(si * sj);
+        pl.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
+        pl.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
+        pl.same_label = false;
+    }
     load_row<NV>(in.emb, j, d4, l, pl.ej);
 }
 
@@ -170,21 +191,32 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
     }
 }
 
+// The training signal of the fused pass: with TRAIN, grad_fused[p] is not read but formed
+// from the pair's own fused value: the margin contrastive loss in similarity form on
+// same-label pairs (y (1 - f)^2 + (1 - y) max(0, f - margin)^2, averaged over P), whose sum
+// goes to one float64 partial per block; fused[p] is written when non-NULL.
+struct TrainOut {
+    float margin, inv_P;
+    float *fused;
+    double *loss_partial;
+};
+
+
 // First pass of the backward, over the pairs in order of their first index i (order_i):
 // recomputes the forward, accumulates e_i's gradient in registers over its row, and stores
 // per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
 // feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
-template <int NV, int UNITS>
+template <int NV, int UNITS, bool TRAIN>
 __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
                                                                 const uint64_t *__restrict__ order_i,
                                                                 float4 *__restrict__ pack, float4 *__restrict__ feat,
-                                                                float *__restrict__ demb) {
+                                                                float *__restrict__ demb, TrainOut tr) {
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
     const int64_t chunk = ceil_div(in.P, ngroups);
     const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
-    if (q0 >= q1) return;
+    double loss_acc = 0.0;
     const int d4 = in.d >> 2;
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
@@ -208,7 +240,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
             load_pair<NV>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
-            gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
+            if (!TRAIN) gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
@@ -218,6 +250,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
                 if (l == 0) {
                     pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
                     feat[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (TRAIN && tr.fused) tr.fused[p] = __builtin_nanf("");
                 }
                 continue;
             }
@@ -232,7 +265,26 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             }
             PairState<UNITS> st;
             pair_forward<NV, UNITS>(ei, ni2, pl[u], W1, b1, w2, b2, st);
-            const float gf = gfb[u];
+            float gf;
+            if (TRAIN) {
+                const float f = st.g * pl[u].s + st.gm * st.c;
+                float lp;
+                if (pl[u].same_label) {
+                    const float e = 1.f - f;
+                    lp = e * e;
+                    gf = -2.f * e * tr.inv_P;
+                } else {
+                    const float h = fmaxf(f - tr.margin, 0.f);
+                    lp = h * h;
+                    gf = 2.f * h * tr.inv_P;
+                }
+                if (l == 0) {
+                    loss_acc += (double)lp;
+                    if (tr.fused) tr.fused[p] = f;
+                }
+            } else {
+                gf = gfb[u];
+            }
             const float ubar = gf * (pl[u].s - st.c) * st.g * st.gm;
             float xc = 0.f;
 #pragma unroll
@@ -258,6 +310,16 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     if (cur_i >= 0 && demb) {
         const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
         flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here && ends_here);
+    }
+    if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
+        __shared__ double red[kGateThreads];
+        red[threadIdx.x] = loss_acc;
+        __syncthreads();
+        for (int o = kGateThreads / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tr.loss_partial[blockIdx.x] = red[0];
     }
 }
 
@@ -380,8 +442,10 @@ static int gate_validate(const GateIn &in) {
     return SUBQUAD_OK;
 }
 
+static int64_t gate_max_blocks();
+
 static int64_t gate_blocks(int64_t P, const void *kernel) {
-    return gate_blocks_resident(P, knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU), kernel);
+    return std::min<int64_t>(gate_blocks_resident(P, knob(SUBQUAD_KNOB_GATE_GROUPS_PER_CU), kernel), gate_max_blocks());
 }
 
 template <int NV>
@@ -403,16 +467,18 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
     return SUBQUAD_OK;
 }
 
-template <int NV>
-static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_i, const uint64_t *order_j, float4 *pack,
-                       float4 *feat, float *demb, double *wacc, hipStream_t st) {
+template <int NV, bool TRAIN>
+static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, int64_t *lblocks, const uint64_t *order_i,
+                       const uint64_t *order_j, float4 *pack, float4 *feat, float *demb, double *wacc, hipStream_t st) {
     switch (in.H / kGroup) {
 #define SQ_CASE(U)                                                                                                 \
     case U: {                                                                                                      \
         {                                                                                                          \
-            const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U>);                        \
+            const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U, TRAIN>);                 \
+            if (lblocks) *lblocks = blocks;                                                                        \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
-            gate_bwd_kernel<NV, U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, feat, demb);   \
+            gate_bwd_kernel<NV, U, TRAIN><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, feat,  \
+                                                                                    demb, tr);                     \
         }                                                                                                          \
         SQ_LAUNCHED("gate_bwd_kernel");                                                                            \
         {                                                                                                          \
@@ -439,11 +505,14 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const uint64_t *order_
     return SUBQUAD_OK;
 }
 
+// Most blocks any chunked gate kernel is launched with (the resident-round cap).
+static int64_t gate_max_blocks() { return (int64_t)device_cus() * 8; }
+
 struct GateBwdLayout {
-    size_t wacc, ra, rb, rc, rd, pack, feat, radix, total;
+    size_t wacc, ra, rb, rc, rd, pack, feat, node, lpart, radix, total;
 };
 
-static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P) {
+static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
     GateBwdLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
@@ -454,6 +523,8 @@ static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P) {
     L.rd = take(sizeof(uint64_t) * P);
     L.pack = take(sizeof(float4) * P);
     L.feat = take(sizeof(float4) * P);
+    L.node = take(sizeof(int4) * n);
+    L.lpart = take(sizeof(double) * (size_t)gate_max_blocks());
     L.radix = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
     L.total = off;
     return L;
@@ -558,9 +629,74 @@ extern "C" int subquad_gate_fwd(const float *emb, int64_t n, int32_t d, const in
     return gate_fwd_nv<16>(in, fused, gate, st);
 }
 
-extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P) {
-    if (H <= 0 || P < 0 || P >= (int64_t(1) << 32)) return 0;
-    return gate_bwd_layout(H, P).total;
+extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P, int64_t n) {
+    if (H <= 0 || P < 0 || n < 0 || P >= (int64_t(1) << 32)) return 0;
+    return gate_bwd_layout(H, P, n).total;
+}
+
+// The backward (TRAIN = false: upstream gradient given) or the fused training pass.
+template <bool TRAIN>
+static int gate_backward(const GateIn &in0, const int32_t *label, const float *grad_fused, float margin, float *fused,
+                         double *loss, float *dW1, float *db1, float *dw2, float *db2, float *demb, void *ws,
+                         size_t ws_bytes, void *stream) {
+    GateIn in = in0;
+    int rc = gate_validate(in);
+    if (rc != SUBQUAD_OK) return rc;
+    SQ_REQUIRE(dW1 && db1 && dw2 && db2, SUBQUAD_ERR_ARG, "null weight-gradient pointer");
+    if (TRAIN) {
+        SQ_REQUIRE(loss, SUBQUAD_ERR_ARG, "null loss pointer");
+        SQ_REQUIRE(in.P == 0 || label, SUBQUAD_ERR_ARG, "null label pointer");
+        SQ_REQUIRE(margin == margin, SUBQUAD_ERR_ARG, "margin is NaN");
+    } else {
+        SQ_REQUIRE(in.P == 0 || grad_fused, SUBQUAD_ERR_ARG, "null grad_fused");
+    }
+    SQ_REQUIRE(in.P < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "P must be below 2^32");
+    const GateBwdLayout L = gate_bwd_layout(in.H, in.P, in.n);
+    SQ_REQUIRE(ws && ws_bytes >= L.total, SUBQUAD_ERR_WORKSPACE, "gate workspace of %zu bytes, %zu needed", ws_bytes,
+               L.total);
+    SQ_REQUIRE(((uintptr_t)ws & 255) == 0, SUBQUAD_ERR_ARG, "workspace must be 256-byte aligned");
+    SQ_REQUIRE(demb == nullptr || ((uintptr_t)demb & 15) == 0, SUBQUAD_ERR_ARG, "demb must be 16-byte aligned");
+    hipStream_t st = as_stream(stream);
+    char *w = static_cast<char *>(ws);
+    double *lpart = reinterpret_cast<double *>(w + L.lpart);
+    if (in.P == 0) {
+        if (TRAIN) {
+            contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, 0, 0, loss);
+            SQ_LAUNCHED("contrastive_final_kernel");
+        }
+        return SUBQUAD_OK;
+    }
+    double *wacc = reinterpret_cast<double *>(w + L.wacc);
+    gate_ws_zero_kernel<<<1, 256, 0, st>>>(wacc, in.H * 6 + 1);
+    SQ_LAUNCHED("gate_ws_zero_kernel");
+    int4 *node = reinterpret_cast<int4 *>(w + L.node);
+    if (in.n > 0) {
+        gate_node_pack_kernel<<<(unsigned)std::min<int64_t>(ceil_div(in.n, 256), (int64_t)device_cus() * 16), 256, 0,
+                                st>>>(in.self, in.lens, in.vgene, TRAIN ? label : nullptr, in.n, node);
+        SQ_LAUNCHED("gate_node_pack_kernel");
+    }
+    in.node = node;
+    uint64_t *order_i = nullptr, *order_j = nullptr;
+    rc = gate_pair_orders(in.pairs, in.P, in.n, w, L, st, &order_i, &order_j);
+    if (rc != SUBQUAD_OK) return rc;
+    float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
+    float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
+    const TrainOut tr{margin, 1.f / (float)in.P, fused, lpart};
+    int64_t lblocks = 0;
+    const int nv = (int)ceil_div(in.d / 4, kGroup);
+    if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    else rc = gate_bwd_nv<16, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    if (rc != SUBQUAD_OK) return rc;
+    gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, in.H, dW1, db1, dw2, db2);
+    SQ_LAUNCHED("gate_ws_finish_kernel");
+    if (TRAIN) {
+        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, (int)lblocks, in.P, loss);
+        SQ_LAUNCHED("contrastive_final_kernel");
+    }
+    return SUBQUAD_OK;
 }
 
 extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lens, const int32_t *vgene,
@@ -569,38 +705,20 @@ extern "C" int subquad_gate_bwd(const float *emb, int64_t n, int32_t d, const in
                                 const float *grad_fused, float *dW1, float *db1, float *dw2, float *db2, float *demb,
                                 void *ws, size_t ws_bytes, void *stream) {
     clear_error();
-    GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H};
-    int rc = gate_validate(in);
-    if (rc != SUBQUAD_OK) return rc;
-    SQ_REQUIRE(dW1 && db1 && dw2 && db2, SUBQUAD_ERR_ARG, "null weight-gradient pointer");
-    SQ_REQUIRE(P == 0 || grad_fused, SUBQUAD_ERR_ARG, "null grad_fused");
-    SQ_REQUIRE(P < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "P must be below 2^32");
-    const GateBwdLayout L = gate_bwd_layout(H, P);
-    SQ_REQUIRE(ws && ws_bytes >= L.total, SUBQUAD_ERR_WORKSPACE, "gate workspace of %zu bytes, %zu needed", ws_bytes,
-               L.total);
-    SQ_REQUIRE(((uintptr_t)ws & 255) == 0, SUBQUAD_ERR_ARG, "workspace must be 256-byte aligned");
-    SQ_REQUIRE(demb == nullptr || ((uintptr_t)demb & 15) == 0, SUBQUAD_ERR_ARG, "demb must be 16-byte aligned");
-    if (P == 0) return SUBQUAD_OK;
-    hipStream_t st = as_stream(stream);
-    char *w = static_cast<char *>(ws);
-    double *wacc = reinterpret_cast<double *>(w + L.wacc);
-    gate_ws_zero_kernel<<<1, 256, 0, st>>>(wacc, H * 6 + 1);
-    SQ_LAUNCHED("gate_ws_zero_kernel");
-    uint64_t *order_i = nullptr, *order_j = nullptr;
-    rc = gate_pair_orders(pairs, P, n, w, L, st, &order_i, &order_j);
-    if (rc != SUBQUAD_OK) return rc;
-    float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
-    float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
-    const int nv = (int)ceil_div(d / 4, kGroup);
-    if (nv <= 1) rc = gate_bwd_nv<1>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 2) rc = gate_bwd_nv<2>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 4) rc = gate_bwd_nv<4>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 8) rc = gate_bwd_nv<8>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
-    else rc = gate_bwd_nv<16>(in, grad_fused, order_i, order_j, pack, feat, demb, wacc, st);
-    if (rc != SUBQUAD_OK) return rc;
-    gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, H, dW1, db1, dw2, db2);
-    SQ_LAUNCHED("gate_ws_finish_kernel");
-    return SUBQUAD_OK;
+    const GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H, nullptr};
+    return gate_backward<false>(in, nullptr, grad_fused, 0.f, nullptr, nullptr, dW1, db1, dw2, db2, demb, ws, ws_bytes,
+                                stream);
+}
+
+extern "C" int subquad_gate_train(const float *emb, int64_t n, int32_t d, const int32_t *lens, const int32_t *vgene,
+                                  const int32_t *self, const int32_t *pairs, const int32_t *align, int64_t P,
+                                  const float *W1, const float *b1, const float *w2, const float *b2, int32_t H,
+                                  const int32_t *label, float margin, float *fused, double *loss, float *dW1,
+                                  float *db1, float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    clear_error();
+    const GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H, nullptr};
+    return gate_backward<true>(in, label, nullptr, margin, fused, loss, dW1, db1, dw2, db2, demb, ws, ws_bytes, stream);
 }
 
 extern "C" size_t subquad_contrastive_workspace_bytes(void) { return sizeof(double) * (size_t)contrastive_blocks(); }

@@ -9,8 +9,9 @@
 // Mapping to CDNA4: one wave per sequence, lane l owns hash functions l + 64 j (j < J).
 // Every block regenerates the 60*M table words into LDS as separate hi and lo 32-bit
 // planes, laid out [pos][residue][lane][j], so that a lookup with a wave-uniform residue
-// reads consecutive 4*J-byte words (no bank conflicts).  The sequence row is wave-uniform
-// and comes through scalar loads.  Stores are 512-byte coalesced rows of sig.
+// reads consecutive 4*J-byte words (no bank conflicts).  The sequence row is wave-uniform;
+// it is fetched one sequence ahead with vector loads and kept in registers.  Stores are
+// 512-byte coalesced rows of sig.
 #include "common.h"
 
 namespace subquad {
@@ -70,11 +71,27 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const uint32_t *Hl = Thi + lane * J;
     const uint32_t *Ll = Tlo + lane * J;
 
+    // The sequence row (at most 64 bytes) and length come through vector loads issued one
+    // sequence ahead: they wait on the vector-memory counter, which the LDS lookups of the
+    // current sequence never wait on, so the next row arrives while this one is hashed.
+    const int words = stride >> 2;
+    uint32_t nrow[16];
+    int nlen = 0;
+    auto fetch = [&](int64_t k) {
+        if (k < n) {
+            const uint32_t *r32 = reinterpret_cast<const uint32_t *>(seqs + k * (int64_t)stride);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) nrow[q] = q < words ? r32[q] : 0u;  // never past the row
+            nlen = lens[k];
+        }
+    };
+    fetch(wave);
     for (int64_t i = wave; i < n; i += nwaves) {
-        const uint8_t *row8 = seqs + i * (int64_t)stride;
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(row8);
-        const int L = __builtin_amdgcn_readfirstlane(lens[i]);
-        const int words = stride >> 2;
+        uint32_t row[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) row[q] = __builtin_amdgcn_readfirstlane(nrow[q]);
+        const int L = __builtin_amdgcn_readfirstlane(nlen);
+        fetch(i + nwaves);
         const int nsh = L - 2;  // shingles
         uint32_t m1[J], m2[J], arg[J];
 #pragma unroll
@@ -88,8 +105,13 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
 #pragma unroll 1
         for (int q = 0; q < nsh; q += 4) {
             const int w = q >> 2;
-            const uint32_t w0 = __builtin_amdgcn_readfirstlane(row[w]);
-            const uint32_t w1 = w + 1 < words ? __builtin_amdgcn_readfirstlane(row[w + 1]) : 0u;
+            uint32_t w0 = row[0], w1 = row[1];
+#pragma unroll
+            for (int k = 1; k < 15; ++k) {  // wave-uniform selects of row[w], row[w + 1]
+                w0 = w == k ? row[k] : w0;
+                w1 = w == k ? row[k + 1] : w1;
+            }
+            if (w == 15) { w0 = row[15]; w1 = 0u; }
             uint32_t off[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
@@ -121,13 +143,20 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int t = lane + 64 * j;
-            // lo half of the winning shingle (per-lane position; the row is in cache)
-            const uint32_t a0 = min((uint32_t)row8[arg[j]], 19u);
-            const uint32_t a1 = min((uint32_t)row8[arg[j] + 1], 19u);
-            const uint32_t a2 = min((uint32_t)row8[arg[j] + 2], 19u);
+            // lo half of the winning shingle: its three residues from the row words in registers
+            const uint32_t a = arg[j], wa = a >> 2;
+            uint32_t lo0 = row[0], hi0 = row[1];
+#pragma unroll
+            for (int k = 1; k < 16; ++k) {
+                lo0 = wa == (uint32_t)k ? row[k] : lo0;
+                hi0 = wa == (uint32_t)k ? (k + 1 < 16 ? row[k + 1] : 0u) : hi0;
+            }
+            const uint32_t tri = (uint32_t)((((uint64_t)hi0 << 32) | lo0) >> (8 * (a & 3u)));
+            const uint32_t a0 = min(tri & 0xFFu, 19u), a1 = min((tri >> 8) & 0xFFu, 19u), a2 = min((tri >> 16) & 0xFFu, 19u);
             uint32_t lo = Ll[a0 * (64 * J) + j] ^ Ll[kRole + a1 * (64 * J) + j] ^ Ll[2 * kRole + a2 * (64 * J) + j];
             uint64_t best = ((uint64_t)m1[j] << 32) | lo;
             if (m1[j] == m2[j]) {  // rare: exact 64-bit minimum over every position
+                const uint8_t *row8 = seqs + i * (int64_t)stride;
                 best = ~0ull;
                 for (int q = 0; q + 3 <= L; ++q) {
                     const uint32_t b0 = min((uint32_t)row8[q], 19u);
@@ -175,6 +204,7 @@ extern "C" int subquad_minhash(const uint8_t *seqs, const int32_t *lens, int64_t
     SQ_REQUIRE(M >= 1 && M <= 256, SUBQUAD_ERR_ARG, "M must be in 1..256 (got %d)", M);
     SQ_REQUIRE(stride >= 4 && stride <= 64 && stride % 4 == 0, SUBQUAD_ERR_ARG,
                "stride must be a multiple of 4 in 4..64 (got %d)", stride);
+    SQ_REQUIRE(((uintptr_t)seqs & 3) == 0, SUBQUAD_ERR_ARG, "seqs must be 4-byte aligned");
     if (n == 0) return SUBQUAD_OK;
     hipStream_t st = as_stream(stream);
     if (M <= 64) return launch_minhash<1>(seqs, lens, n, stride, M, seed, sig, st);

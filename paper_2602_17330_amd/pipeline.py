@@ -1,11 +1,13 @@
 """The hot path as one object: buffers are allocated once, every stage runs in libsubquad.
 
-    MinHash -> LSH candidates -> self-scores -> Smith-Waterman -> gate forward -> gate backward
+    MinHash -> LSH candidates -> self-scores -> Smith-Waterman -> gate (forward, loss, backward)
 
 A ``Pipeline`` owns the device buffers of one batch of repertoires (signatures, LSH and
 alignment workspaces, candidate pairs, scores, fused affinities, gradients), so repeated
-steps allocate nothing.  ``step`` runs the whole path once; ``stage_events`` records a HIP
-event after every stage on the current stream.
+steps allocate nothing.  ``step`` runs the whole path once and records a HIP event after every
+stage when given events.  The gate stage is one fused pass (forward, contrastive loss and
+backward: ``subquad_gate_train``) unless ``PathConfig.fused_gate`` is False, which runs the
+separate forward, loss and backward entry points instead.
 """
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ import torch
 from . import api
 from ._lib import ERR_CAPACITY, check, lib
 
-STAGES = ("minhash", "lsh", "self", "align", "gate_fwd", "loss", "gate_bwd")
+STAGES = ("minhash", "lsh", "self", "align", "gate")
 
 
 @dataclass
@@ -30,6 +32,7 @@ class PathConfig:
     gap_extend: int = 1
     seed: int = api.HASH_SEED
     margin: float = 0.5
+    fused_gate: bool = True
 
 
 class Pipeline:
@@ -64,7 +67,7 @@ class Pipeline:
         self.scores = torch.empty(cap, dtype=torch.int32, device=dev)
         self.fused = torch.empty(cap, dtype=torch.float32, device=dev)
         self.align_ws = torch.empty(api.align_workspace_bytes(cap), dtype=torch.uint8, device=dev)
-        self.gate_ws = torch.empty(api.gate_bwd_workspace_bytes(self.W[0].shape[0], cap),
+        self.gate_ws = torch.empty(api.gate_bwd_workspace_bytes(self.W[0].shape[0], cap, self.n),
                                    dtype=torch.uint8, device=dev)
         self.grads = [torch.zeros_like(w) for w in self.W] + [torch.zeros_like(self.emb)]
         self.grad_fused_buf = torch.empty(cap, dtype=torch.float32, device=dev)
@@ -118,6 +121,20 @@ class Pipeline:
         if self.P:
             api.gate_bwd(*self.gate_args(), self.grad_fused, grads=tuple(self.grads), ws=self.gate_ws)
 
+    def gate(self):
+        """Gate forward, training loss and backward (fused, or the three separate calls)."""
+        if not self.cfg.fused_gate:
+            self.gate_fwd()
+            self.loss_grad()
+            self.gate_bwd()
+            return
+        for g in self.grads:
+            g.zero_()
+        P = self.P
+        if P:
+            api.gate_train(*self.gate_args(), self.family, self.cfg.margin, fused=self.fused[:P], loss=self.loss,
+                           grads=tuple(self.grads), ws=self.gate_ws)
+
     def lsh_async(self):
         """Graph-capturable candidate stage: no host synchronisation; the pair sort is sized
         for the current capacity and the count/status land in device memory."""
@@ -150,9 +167,7 @@ class Pipeline:
             self.lsh_async()
             self.self_scores()
             self.align()
-            self.gate_fwd()
-            self.loss_grad()
-            self.gate_bwd()
+            self.gate()
         self.graph = g
         return g
 
@@ -164,9 +179,8 @@ class Pipeline:
         return int(self.dev_count.item()), int(self.dev_status.item())
 
     def step(self, events=None):
-        """One pass of the whole hot path. ``events``: list of 7 CUDA events or None."""
-        for k, fn in enumerate((self.minhash, self.lsh, self.self_scores, self.align, self.gate_fwd,
-                                self.loss_grad, self.gate_bwd)):
+        """One pass of the whole hot path. ``events``: one CUDA event per stage (STAGES) or None."""
+        for k, fn in enumerate((self.minhash, self.lsh, self.self_scores, self.align, self.gate)):
             fn()
             if events is not None:
                 events[k].record()

@@ -90,12 +90,20 @@ def test_gate_validation(L):
     assert L.subquad_gate_fwd(*args, 48, FAKE, NULL, NULL) == 1          # H not a multiple of 16
     assert L.subquad_gate_fwd(*args[:2], 130, *args[3:], 64, FAKE, NULL, NULL) == 1  # d % 4
     assert L.subquad_gate_fwd(*args[:-1], NULL, 64, FAKE, NULL, NULL) == 1          # null b2
-    assert L.subquad_gate_bwd_workspace_bytes(64, 0) >= 8 * (64 * 6 + 1)
-    assert L.subquad_gate_bwd_workspace_bytes(64, 5000) >= 5000 * (4 * 8 + 16)
-    assert L.subquad_gate_bwd_workspace_bytes(64, -1) == 0
-    ws = L.subquad_gate_bwd_workspace_bytes(64, 5)
+    assert L.subquad_gate_bwd_workspace_bytes(64, 0, 10) >= 8 * (64 * 6 + 1)
+    assert L.subquad_gate_bwd_workspace_bytes(64, 5000, 10) >= 5000 * (4 * 8 + 16)
+    assert L.subquad_gate_bwd_workspace_bytes(64, -1, 10) == 0
+    assert L.subquad_gate_bwd_workspace_bytes(64, 5, -1) == 0
+    ws = L.subquad_gate_bwd_workspace_bytes(64, 5, 10)
     assert L.subquad_gate_bwd(*args, 64, FAKE, FAKE, FAKE, FAKE, FAKE, NULL, 4096, ws - 1, NULL) == 5
     assert L.subquad_gate_bwd(*args, 64, FAKE, NULL, FAKE, FAKE, FAKE, NULL, 4096, ws, NULL) == 1
+    m = ctypes.c_float(0.5)
+    assert L.subquad_gate_train(*args, 64, FAKE, m, NULL, FAKE, FAKE, FAKE, FAKE, FAKE, NULL, 4096, ws - 1,
+                                NULL) == 5
+    assert L.subquad_gate_train(*args, 64, FAKE, m, NULL, NULL, FAKE, FAKE, FAKE, FAKE, NULL, 4096, ws,
+                                NULL) == 1                                         # null loss
+    assert L.subquad_gate_train(*args, 64, NULL, m, NULL, FAKE, FAKE, FAKE, FAKE, FAKE, NULL, 4096, ws,
+                                NULL) == 1                                         # null labels
 
 
 def test_check_seqs_validation(L):

@@ -241,3 +241,58 @@ def test_contrastive_grad():
     g0, l0 = sq.api.contrastive_grad(dev(f[:0]), dev(pairs[:0]), dev(rep.family.astype(np.int32)), 0.5)
     torch.cuda.synchronize()
     assert g0.shape == (0,) and l0.item() == 0.0
+
+
+def _train_oracle(c, labels, margin=0.5):
+    f64 = ogate.forward(**oracle_args(c))
+    y = (labels[c["pairs"][:, 0]] == labels[c["pairs"][:, 1]]).astype(np.float64)
+    L, gl = ogate.contrastive_loss(f64, y, margin)
+    return f64, L, ogate.backward(**oracle_args(c), grad_f=gl)
+
+
+@pytest.mark.parametrize("d,H", [(64, 64), (128, 64), (100, 32)])
+def test_gate_train_against_oracle(d, H):
+    """The fused training pass: forward values, mean contrastive loss and gradients against
+    the oracle's forward, loss and backward (pairs whose ReLU decision is ambiguous at float32
+    precision set aside, as for the backward)."""
+    rep = synth.tiny(n_families=60, fam_size=8, seed=d + 7 * H)
+    full = make_case(rep, d, H, 3000, seed=d + 2, scale_norms=True)
+    c, amb = split_ambiguous(full)
+    say(f"gate train d={d} H={H} (ambiguous ReLU pairs set aside: {len(amb)})")
+    fused, loss, grads = sq.api.gate_train(*gpu_args(c), dev(rep.family.astype(np.int32)), 0.5)
+    torch.cuda.synchronize()
+    f64, L, ref = _train_oracle(c, rep.family)
+    ok, err = fused_tol_ok(fused.cpu().numpy(), f64)
+    assert ok, err
+    assert abs(loss.item() - L) <= 1e-5 * abs(L) + 1e-7
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
+        assert ok, (name, rel)
+
+
+def test_gate_train_matches_separate_calls():
+    """Fused pass = forward, then the contrastive gradient, then the backward: the same fused
+    values bit for bit, the same loss and gradients up to summation order."""
+    rep = synth.tiny(seed=31)
+    c = make_case(rep, 128, 64, 4000, seed=31)
+    lab = dev(rep.family.astype(np.int32))
+    say("gate train vs separate calls")
+    fused, loss, grads = sq.api.gate_train(*gpu_args(c), lab, 0.5)
+    f2 = sq.gate_fwd(*gpu_args(c))
+    gf, l2 = sq.api.contrastive_grad(f2, dev(c["pairs"]), lab, 0.5)
+    g2 = sq.gate_bwd(*gpu_args(c), gf)
+    torch.cuda.synchronize()
+    assert torch.equal(fused, f2)
+    assert abs(loss.item() - l2.item()) <= 1e-12 * abs(l2.item())
+    for a, b in zip(grads, g2):
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(b.abs().max()))
+
+
+def test_gate_train_empty():
+    rep = synth.tiny(seed=32)
+    c = make_case(rep, 64, 64, 100, seed=32)
+    c = dict(c, pairs=np.zeros((0, 2), np.int32), align=np.zeros(0, np.int32))
+    say("gate train P=0")
+    fused, loss, grads = sq.api.gate_train(*gpu_args(c), dev(rep.family.astype(np.int32)), 0.5)
+    torch.cuda.synchronize()
+    assert fused.shape == (0,) and loss.item() == 0.0 and not grads[4].any()
