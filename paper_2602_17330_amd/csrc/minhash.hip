@@ -9,8 +9,8 @@
 // Mapping to CDNA4: one wave per sequence, lane l owns hash functions l + 64 j (j < J).
 // Every block regenerates the 60*M table words into LDS as separate hi and lo 32-bit
 // planes, laid out [pos][residue][lane][j], so that a lookup with a wave-uniform residue
-// reads consecutive 4*J-byte words (no bank conflicts).  The sequence row is wave-uniform;
-// it is fetched one sequence ahead with vector loads and kept in registers.  Stores are
+// reads consecutive 4*J-byte words (no bank conflicts).  Rows reach a wave in groups of
+// consecutive sequences, one coalesced load per group issued a group ahead.  Stores are
 // 512-byte coalesced rows of sig.
 #include "common.h"
 
@@ -26,6 +26,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t q) {
 }
 
 constexpr int kMinhashBlock = 512;
+constexpr uint32_t kPosMask = 63u;  // shingle positions 0..61 (stride <= 64)
 
 // Median of three unsigned words (one VALU instruction).
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
@@ -34,12 +35,32 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
     return r;
 }
 
+// A lane's J consecutive table words in one LDS access (8 or 16 bytes for J = 2 or 4).
+template <int J>
+__device__ __forceinline__ void lds_words(const uint32_t *p, uint32_t (&v)[J]) {
+    if constexpr (J == 1) {
+        v[0] = p[0];
+    } else if constexpr (J == 2) {
+        const uint2 t = *reinterpret_cast<const uint2 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        const uint4 t = *reinterpret_cast<const uint4 *>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+        v[3] = t.w;
+    }
+}
+
 // The signature word is compared as (hi, lo) 32-bit halves.  The streaming pass reads only
-// the hi halves of the tables and keeps, per hash function, the smallest hi value m1, the
-// second smallest m2 (v_med3 of m1, m2 and the new value) and the position of m1.  When
-// m1 != m2 the minimum hash is unique in its hi half, so its lo half is the lo half at that
-// position, read once at the end.  When m1 == m2 (a repeated 3-mer, or two 3-mers whose
-// hashes share the hi half) that lane redoes the sequence with full 64-bit words.
+// the hi halves of the tables; per hash function it keeps the smallest and second smallest
+// of the words (top 26 bits of hi | shingle position): m1 and m2 (v_med3 of m1, m2 and the
+// new word), so m1 carries its own position.  When m1 and m2 differ in the top 26 bits, the
+// shingle at m1's position has the strictly smallest hi half, hence the minimum hash, whose
+// full 64 bits are read once at the end.  Otherwise (a repeated 3-mer, or two 3-mers whose
+// hashes agree in those bits) that lane redoes the sequence with full 64-bit words, taking
+// the residues from the row words the wave already holds.
 template <int J>
 __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const uint8_t *__restrict__ seqs, const int32_t *__restrict__ lens, int64_t n, int32_t stride,
@@ -71,103 +92,117 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const uint32_t *Hl = Thi + lane * J;
     const uint32_t *Ll = Tlo + lane * J;
 
-    // The sequence row (at most 64 bytes) and length come through vector loads issued one
-    // sequence ahead: they wait on the vector-memory counter, which the LDS lookups of the
-    // current sequence never wait on, so the next row arrives while this one is hashed.
-    const int words = stride >> 2;
-    uint32_t nrow[16];
+    // Sequences go to waves in groups of G consecutive rows, G = 64 / D with D = stride / 4
+    // words per row: one coalesced dword load per lane brings a whole group (lane k D + w holds
+    // word w of row k), issued a group ahead; the hashing loop reads words with readlane at
+    // wave-uniform indices, and each lane fetches the words around its winning shingle from
+    // the lane that holds them (ds_bpermute).  The wait for that load (which on this ISA also
+    // waits for the signature stores) thus comes once per group.
+    const int D = stride >> 2;
+    const int G = 64 / D;
+    const int64_t ngroups = ceil_div(n, (int64_t)G);
+    uint32_t nrow = 0u;
     int nlen = 0;
-    auto fetch = [&](int64_t k) {
-        if (k < n) {
-            const uint32_t *r32 = reinterpret_cast<const uint32_t *>(seqs + k * (int64_t)stride);
-#pragma unroll
-            for (int q = 0; q < 16; ++q) nrow[q] = q < words ? r32[q] : 0u;  // never past the row
-            nlen = lens[k];
+    auto fetch = [&](int64_t g) {
+        nrow = 0u;
+        nlen = 0;
+        if (g < ngroups) {
+            const int64_t base = g * G;
+            const int k = lane / D;
+            if (k < G && base + k < n) nrow = reinterpret_cast<const uint32_t *>(seqs + base * (int64_t)stride)[lane];
+            if (lane < G && base + lane < n) nlen = lens[base + lane];
         }
     };
     fetch(wave);
-    for (int64_t i = wave; i < n; i += nwaves) {
-        uint32_t row[16];
+    for (int64_t g = wave; g < ngroups; g += nwaves) {
+        const uint32_t rowv = nrow;
+        const int lenv = nlen;
+        fetch(g + nwaves);
+        const int64_t base = g * G;
+        const int gn = (int)min((int64_t)G, n - base);
+        for (int k = 0; k < gn; ++k) {
+            const int64_t i = base + k;
+            const int L = __builtin_amdgcn_readlane(lenv, k);
+            const int kD = k * D;
+            const int nsh = L - 2;  // shingles
+            uint32_t m1[J], m2[J];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) row[q] = __builtin_amdgcn_readfirstlane(nrow[q]);
-        const int L = __builtin_amdgcn_readfirstlane(nlen);
-        fetch(i + nwaves);
-        const int nsh = L - 2;  // shingles
-        uint32_t m1[J], m2[J], arg[J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-            m1[j] = ~0u;
-            m2[j] = ~0u;
-            arg[j] = 0;
-        }
-        // Four shingles per iteration: residues q .. q+5 come from two row words, and all
-        // twelve lookups are issued before any is used.
+            for (int j = 0; j < J; ++j) {
+                m1[j] = ~0u;
+                m2[j] = ~0u;
+            }
+            // Four shingles per iteration: residues q .. q+5 come from two row words, and all
+            // twelve lookups are issued before any is used.
 #pragma unroll 1
-        for (int q = 0; q < nsh; q += 4) {
-            const int w = q >> 2;
-            uint32_t w0 = row[0], w1 = row[1];
+            for (int q = 0; q < nsh; q += 4) {
+                const int w = q >> 2;
+                const uint32_t w0 = __builtin_amdgcn_readlane(rowv, kD + w);
+                const uint32_t w1 = w + 1 < D ? __builtin_amdgcn_readlane(rowv, kD + w + 1) : 0u;
+                uint32_t off[6];
 #pragma unroll
-            for (int k = 1; k < 15; ++k) {  // wave-uniform selects of row[w], row[w + 1]
-                w0 = w == k ? row[k] : w0;
-                w1 = w == k ? row[k + 1] : w1;
-            }
-            if (w == 15) { w0 = row[15]; w1 = 0u; }
-            uint32_t off[6];
+                for (int e = 0; e < 6; ++e) {
+                    uint32_t c = e < 4 ? (w0 >> (8 * e)) & 0xFFu : (w1 >> (8 * (e - 4))) & 0xFFu;
+                    off[e] = (c < 20u ? c : 19u) * (64 * J);
+                }
+                uint32_t h[4][J];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                uint32_t c = k < 4 ? (w0 >> (8 * k)) & 0xFFu : (w1 >> (8 * (k - 4))) & 0xFFu;
-                off[k] = (c < 20u ? c : 19u) * (64 * J);
-            }
-            uint32_t h[4][J];
+                for (int sh = 0; sh < 4; ++sh) {
+                    uint32_t t0[J], t1[J], t2[J];
+                    lds_words<J>(Hl + off[sh], t0);
+                    lds_words<J>(Hl + kRole + off[sh + 1], t1);
+                    lds_words<J>(Hl + 2 * kRole + off[sh + 2], t2);
 #pragma unroll
-            for (int sh = 0; sh < 4; ++sh) {
+                    for (int j = 0; j < J; ++j) h[sh][j] = t0[j] ^ t1[j] ^ t2[j];
+                }
+                const int live = min(4, nsh - q);  // wave-uniform
 #pragma unroll
-                for (int j = 0; j < J; ++j)
-                    h[sh][j] = Hl[off[sh] + j] ^ Hl[kRole + off[sh + 1] + j] ^ Hl[2 * kRole + off[sh + 2] + j];
-            }
-            const int live = min(4, nsh - q);  // wave-uniform
+                for (int sh = 0; sh < 4; ++sh) {
+                    if (sh < live) {
 #pragma unroll
-            for (int sh = 0; sh < 4; ++sh) {
-                if (sh < live) {
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const uint32_t v = h[sh][j];
-                        arg[j] = v < m1[j] ? (uint32_t)(q + sh) : arg[j];
-                        m2[j] = umed3(m1[j], m2[j], v);
-                        m1[j] = min(m1[j], v);
+                        for (int j = 0; j < J; ++j) {
+                            // top 26 bits of the hi half, shingle position in the low 6
+                            const uint32_t v = (h[sh][j] & ~kPosMask) | (uint32_t)(q + sh);
+                            m2[j] = umed3(m1[j], m2[j], v);
+                            m1[j] = min(m1[j], v);
+                        }
                     }
                 }
             }
-        }
-        uint64_t *out = sig + i * (int64_t)M;
+            uint64_t *out = sig + i * (int64_t)M;
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const int t = lane + 64 * j;
-            // lo half of the winning shingle: its three residues from the row words in registers
-            const uint32_t a = arg[j], wa = a >> 2;
-            uint32_t lo0 = row[0], hi0 = row[1];
-#pragma unroll
-            for (int k = 1; k < 16; ++k) {
-                lo0 = wa == (uint32_t)k ? row[k] : lo0;
-                hi0 = wa == (uint32_t)k ? (k + 1 < 16 ? row[k + 1] : 0u) : hi0;
-            }
-            const uint32_t tri = (uint32_t)((((uint64_t)hi0 << 32) | lo0) >> (8 * (a & 3u)));
-            const uint32_t a0 = min(tri & 0xFFu, 19u), a1 = min((tri >> 8) & 0xFFu, 19u), a2 = min((tri >> 16) & 0xFFu, 19u);
-            uint32_t lo = Ll[a0 * (64 * J) + j] ^ Ll[kRole + a1 * (64 * J) + j] ^ Ll[2 * kRole + a2 * (64 * J) + j];
-            uint64_t best = ((uint64_t)m1[j] << 32) | lo;
-            if (m1[j] == m2[j]) {  // rare: exact 64-bit minimum over every position
-                const uint8_t *row8 = seqs + i * (int64_t)stride;
-                best = ~0ull;
-                for (int q = 0; q + 3 <= L; ++q) {
-                    const uint32_t b0 = min((uint32_t)row8[q], 19u);
-                    const uint32_t b1 = min((uint32_t)row8[q + 1], 19u);
-                    const uint32_t b2 = min((uint32_t)row8[q + 2], 19u);
-                    const int o0 = b0 * (64 * J) + j, o1 = kRole + b1 * (64 * J) + j, o2 = 2 * kRole + b2 * (64 * J) + j;
-                    uint64_t h = ((uint64_t)(Hl[o0] ^ Hl[o1] ^ Hl[o2]) << 32) | (Ll[o0] ^ Ll[o1] ^ Ll[o2]);
-                    best = h < best ? h : best;
+            for (int j = 0; j < J; ++j) {
+                const int t = lane + 64 * j;
+                // lo half of the winning shingle: its three residues, from the lanes holding
+                // words position/4 and position/4 + 1 of this row
+                const uint32_t a = m1[j] & kPosMask, wa = a >> 2;
+                const uint32_t lo0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((kD + wa) * 4), (int)rowv);
+                uint32_t hi0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((kD + wa + 1) * 4), (int)rowv);
+                if (wa + 1 >= (uint32_t)D) hi0 = 0u;
+                const uint32_t tri = (uint32_t)((((uint64_t)hi0 << 32) | lo0) >> (8 * (a & 3u)));
+                const uint32_t a0 = min(tri & 0xFFu, 19u), a1 = min((tri >> 8) & 0xFFu, 19u),
+                               a2 = min((tri >> 16) & 0xFFu, 19u);
+                const int o0 = a0 * (64 * J) + j, o1 = kRole + a1 * (64 * J) + j, o2 = 2 * kRole + a2 * (64 * J) + j;
+                const uint32_t hi = Hl[o0] ^ Hl[o1] ^ Hl[o2];  // the full hi half (its low 6 bits were replaced)
+                const uint32_t lo = Ll[o0] ^ Ll[o1] ^ Ll[o2];
+                uint64_t best = ((uint64_t)hi << 32) | lo;
+                if ((m1[j] >> 6) == (m2[j] >> 6)) {  // a tie in the top bits: exact 64-bit minimum over every position
+                    best = ~0ull;
+                    for (int q = 0; q + 3 <= L; ++q) {  // residues from the row words (no memory access)
+                        const int w = q >> 2;
+                        const uint32_t wl = __builtin_amdgcn_readlane(rowv, kD + w);
+                        const uint32_t wh = w + 1 < D ? __builtin_amdgcn_readlane(rowv, kD + w + 1) : 0u;
+                        const uint32_t tq = (uint32_t)((((uint64_t)wh << 32) | wl) >> (8 * (q & 3)));
+                        const uint32_t b0 = min(tq & 0xFFu, 19u);
+                        const uint32_t b1 = min((tq >> 8) & 0xFFu, 19u);
+                        const uint32_t b2 = min((tq >> 16) & 0xFFu, 19u);
+                        const int e0 = b0 * (64 * J) + j, e1 = kRole + b1 * (64 * J) + j,
+                                  e2 = 2 * kRole + b2 * (64 * J) + j;
+                        uint64_t hh = ((uint64_t)(Hl[e0] ^ Hl[e1] ^ Hl[e2]) << 32) | (Ll[e0] ^ Ll[e1] ^ Ll[e2]);
+                        best = hh < best ? hh : best;
+                    }
                 }
+                if (t < M) out[t] = best;
             }
-            if (t < M) out[t] = best;
         }
     }
 }
@@ -184,7 +219,8 @@ static int launch_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, i
     }
     const int waves_per_block = kMinhashBlock / kWave;
     const int per_cu = J <= 2 ? std::min(knob(SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU), 2) : 1;  // LDS bound
-    int64_t blocks = std::min<int64_t>(ceil_div(n, waves_per_block), (int64_t)device_cus() * per_cu);
+    const int64_t groups = ceil_div(n, (int64_t)(64 / (stride / 4)));  // rows per wave group: 64 / (stride / 4)
+    int64_t blocks = std::min<int64_t>(ceil_div(groups, waves_per_block), (int64_t)device_cus() * per_cu);
     ProfScope prof("minhash3_kernel", st);
     minhash3_kernel<J><<<(unsigned)blocks, kMinhashBlock, lds, st>>>(seqs, lens, n, stride, M, seed, sig);
     SQ_LAUNCHED("minhash3_kernel");
