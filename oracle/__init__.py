@@ -14,4 +14,4 @@ Parity status: every function here is pinned by CPU tests against values fixed b
 mathematics (brute force on tiny inputs, closed forms, textbook special cases, published
 generator outputs, invariants); see ``tests/test_oracle_*.py``.
 """
-from . import edit, gate, graph, lsh, minhash, proto, sw  # noqa: F401
+from . import edit, gate, graph, lsh, minhash, proto, rmt, sw  # noqa: F401
