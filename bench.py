@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
     ap.add_argument("--no-proto", action="store_true", help="skip the prototype-loss measurement")
+    ap.add_argument("--no-rmt", action="store_true", help="skip the RMT edge-threshold measurement")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run N elementwise copies of 1 GiB (y = x * 1 over 2^28 float32: 1 GiB read, "
                          "1 GiB written) to calibrate the HBM byte counters")
@@ -240,6 +241,37 @@ def proto_leg(torch, sq, rep, emb, steps, warmup):
     return dict(workload=f"{rep.n} rows, C={C} classes (families), B={B}, d={d}, tau=0.1, fp32 MFMA",
                 step_ms=wall * 1e3, rows_per_s=B / wall, tflops_step=total_flops / wall / 1e12,
                 kernels=kernels)
+
+
+def rmt_leg(torch, sq, pipe):
+    """RMT edge threshold (Sec. 3.7) of the bench step's own similarity graph: every positive
+    fused affinity of its candidate pairs, both directions; 64 Lanczos steps per largest
+    eigenvalue, 20 bisection steps."""
+    from paper_2602_17330_amd import _lib, api
+    P = pipe.P
+    rows, cols, vals = api.graph_topk(pipe.pairs[:P], pipe.fused[:P], pipe.n, tau=0.0, k=0)
+    torch.cuda.synchronize()
+    api.rmt_threshold(rows, cols, vals, pipe.n, iters=2)  # warm-up
+    torch.cuda.synchronize()
+    _lib.profile_enable(True)
+    t0 = time.perf_counter()
+    tau, lp, lmax = api.rmt_threshold(rows, cols, vals, pipe.n)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern = _lib.profile_report()
+    _lib.profile_enable(False)
+    nnz = int(vals.shape[0])
+    n = pipe.n
+    launches, total_ms = kern.get("rmt_spmv_kernel", (0, 0.0))
+    avg = total_ms / max(launches, 1)
+    alg = nnz * 8 + (n + 1) * 8 + n * 8  # (col, value) per entry, row offsets, x read once, y written
+    ach = alg / (avg / 1e3) / 1e9 if avg > 0 else None
+    kept = int((vals >= tau).sum().item()) // 2
+    return dict(workload=f"similarity graph of the bench step: n={n}, {nnz} directed entries, 64 Lanczos steps, "
+                         f"20 bisection steps", ms=wall * 1e3, tau=tau, lambda_plus=lp, lambda_max=lmax,
+                edges_kept=kept, edges_total=nnz // 2, spmv_launches=launches, spmv_avg_ms=avg,
+                spmv_roofline={"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS if ach else None, "alg_bytes_per_launch": alg})
 
 
 def cpu_baseline(rep, emb, S, pipe, cfg):
@@ -462,6 +494,7 @@ def main():
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
     proto = None if a.no_proto else proto_leg(torch, sq, rep, emb, max(3, min(a.steps, 5)), 1)
+    rmt = None if a.no_rmt else rmt_leg(torch, sq, pipe)
     if a.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -492,6 +525,7 @@ def main():
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
         "gate_2p20": gate,
         "proto_loss": proto,
+        "rmt_threshold": rmt,
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,

@@ -340,6 +340,33 @@ int subquad_proto_bwd(const float *emb, int64_t n, int32_t d, const int32_t *lab
                       int32_t through_prototypes, float *demb, void *ws, size_t ws_bytes,
                       void *stream);
 
+/*
+ * RMT edge threshold of the similarity graph (Sec. 3.7; Algorithm 1: the eigenvalue spectrum
+ * of the fused-affinity matrix gives a bulk cutoff; edges below the threshold it implies are
+ * dropped).  Input: the symmetric CSR graph of subquad_graph_topk built with tau = 0, k = 0
+ * (every positive affinity, both directions): row_offsets [n+1] i64, cols [nnz] i32,
+ * vals [nnz] f32 (device).  Readings (the paper names no estimator):
+ *   lambda_plus = 2 sqrt(sum of vals^2 / n), the Wigner semicircle edge at A's mean squared
+ *   row norm; tau* = the largest tau whose lighter edges (0 < a < tau) keep the largest
+ *   eigenvalue inside the bulk (<= lambda_plus), by `iters` bisection steps on [0, max a]
+ *   with float64 midpoints; tau* = max a + 1 (no edge kept) when lambda_max(A) <= lambda_plus.
+ * Each largest eigenvalue comes from `steps` Lanczos steps (float32 vectors, float64 dots,
+ * full reorthogonalisation) from a start vector drawn from SplitMix64 with `seed`.
+ * Outputs are host doubles; the call synchronises `stream` once per Lanczos run.  Keep the
+ * edges with a >= tau* (subquad_graph_topk with tau = tau*).
+ *   steps in 2..128, iters in 0..60;
+ *   ws / ws_bytes: subquad_rmt_workspace_bytes(n, steps) bytes, 256-byte aligned.
+ * subquad_rmt_lambda_max: the largest eigenvalue of A_low(tau) alone (tau = INFINITY: of A).
+ */
+size_t subquad_rmt_workspace_bytes(int64_t n, int32_t steps);
+int subquad_rmt_threshold(const int64_t *row_offsets, const int32_t *cols, const float *vals,
+                          int64_t n, int64_t nnz, int32_t steps, int32_t iters, uint64_t seed,
+                          double *tau, double *lambda_plus, double *lambda_max, void *ws,
+                          size_t ws_bytes, void *stream);
+int subquad_rmt_lambda_max(const int64_t *row_offsets, const int32_t *cols, const float *vals,
+                           int64_t n, int64_t nnz, double tau, int32_t steps, uint64_t seed,
+                           double *lambda_max, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

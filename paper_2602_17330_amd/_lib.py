@@ -55,6 +55,11 @@ SIGNATURES = {
     "subquad_contrastive_workspace_bytes": (c_sz, []),
     "subquad_contrastive_grad": (ctypes.c_int, [c_p, c_p, c_i64, c_p, c_i64, ctypes.c_float, c_p, c_p, c_p, c_sz,
                                                 c_p]),
+    "subquad_rmt_workspace_bytes": (c_sz, [c_i64, c_i32]),
+    "subquad_rmt_threshold": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_i64, c_i32, c_i32, c_u64, c_p, c_p, c_p, c_p,
+                                             c_sz, c_p]),
+    "subquad_rmt_lambda_max": (ctypes.c_int, [c_p, c_p, c_p, c_i64, c_i64, ctypes.c_double, c_i32, c_u64, c_p, c_p,
+                                              c_sz, c_p]),
     "subquad_proto_workspace_bytes": (c_sz, [c_i64, c_i32, c_i64, c_i64]),
     "subquad_proto_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i64, ctypes.c_float, c_p, c_p,
                                          c_p, c_p, c_sz, c_p]),

@@ -290,6 +290,44 @@ def graph_topk(pairs: torch.Tensor, w: torch.Tensor, n: int, tau: float = 0.7, k
 EDIT_INDEL = 2
 
 
+RMT_STEPS = 64
+RMT_ITERS = 20
+RMT_SEED = 2602
+
+
+def rmt_threshold(row_offsets, cols, vals, n: int, steps: int = RMT_STEPS, iters: int = RMT_ITERS,
+                  seed: int = RMT_SEED, ws=None):
+    """(tau*, lambda_plus, lambda_max) of the CSR similarity graph (positive affinities, both
+    directions); keep the edges with weight >= tau*."""
+    row_offsets = _dev(row_offsets, torch.int64, "row_offsets")
+    cols = _dev(cols, torch.int32, "cols")
+    vals = _dev(vals, torch.float32, "vals")
+    need = int(lib().subquad_rmt_workspace_bytes(n, steps))
+    if need == 0:
+        raise SubquadError(1, f"no rmt workspace size for n={n}, steps={steps}")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=vals.device)
+    out = [ctypes.c_double(0.0) for _ in range(3)]
+    check(lib().subquad_rmt_threshold(_ptr(row_offsets), _ptr(cols), _ptr(vals), n, vals.shape[0], steps, iters,
+                                      seed, *[ctypes.byref(o) for o in out], _ptr(ws), ws.numel(), _stream()))
+    return tuple(o.value for o in out)
+
+
+def rmt_lambda_max(row_offsets, cols, vals, n: int, tau: float = float("inf"), steps: int = RMT_STEPS,
+                   seed: int = RMT_SEED, ws=None) -> float:
+    """Largest eigenvalue of the matrix of the edges lighter than tau."""
+    row_offsets = _dev(row_offsets, torch.int64, "row_offsets")
+    cols = _dev(cols, torch.int32, "cols")
+    vals = _dev(vals, torch.float32, "vals")
+    need = int(lib().subquad_rmt_workspace_bytes(n, steps))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=vals.device)
+    out = ctypes.c_double(0.0)
+    check(lib().subquad_rmt_lambda_max(_ptr(row_offsets), _ptr(cols), _ptr(vals), n, vals.shape[0], tau, steps,
+                                       seed, ctypes.byref(out), _ptr(ws), ws.numel(), _stream()))
+    return out.value
+
+
 def edit_cost_matrix(subst) -> np.ndarray:
     """Doubled substitution costs for the edit-distance channel: 0 for a match, 1 for a
     substitution with a positive score (conservative), 2 otherwise; indels cost 2."""

@@ -19,7 +19,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsubquad.so")
 ARCH = os.environ.get("SUBQUAD_ARCH", "gfx950")
 
-SOURCES = ["capi.hip", "minhash.hip", "radix.hip", "lsh.hip", "align.hip", "gate.hip", "gate_m.hip", "graph.hip", "proto.hip"]
+SOURCES = ["capi.hip", "minhash.hip", "radix.hip", "lsh.hip", "align.hip", "gate.hip", "gate_m.hip", "graph.hip", "proto.hip", "rmt.hip"]
 
 # Packed FP32 VALU forms are disabled (-packed-fp32-ops): the compiler otherwise forms
 # v_pk_{add,mul,fma}_f32 from scalar float code.
