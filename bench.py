@@ -84,6 +84,7 @@ def parse():
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
     ap.add_argument("--no-proto", action="store_true", help="skip the prototype-loss measurement")
     ap.add_argument("--no-rmt", action="store_true", help="skip the RMT edge-threshold measurement")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run N elementwise copies of 1 GiB (y = x * 1 over 2^28 float32: 1 GiB read, "
                          "1 GiB written) to calibrate the HBM byte counters")
@@ -442,6 +443,21 @@ def main():
         per += np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(len(STAGES))])
     stage_ms = per / reps
     log(f"step {wall * 1e3:.3f} ms; stages " + ", ".join(f"{s}={m:.3f}" for s, m in zip(STAGES, stage_ms)))
+    # the same step replayed from one HIP graph (no launch gaps), reported beside the eager step
+    graph_ms = None
+    if not a.no_graph:
+        pipe.capture()
+        pipe.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            pipe.replay()
+        torch.cuda.synchronize()
+        graph_ms = (time.perf_counter() - t0) / a.steps * 1e3
+        status = pipe.graph_status()
+        if status != (P, 0):
+            raise RuntimeError(f"graph replay produced {status}, expected ({P}, 0)")
+        log(f"graph-replayed step {graph_ms:.3f} ms")
     log("kernels: " + ", ".join(f"{k}={v[1] / a.steps:.3f}ms/step({v[0] // a.steps}x)" for k, v in kern.items()))
 
     n = rep.n
@@ -523,6 +539,8 @@ def main():
                    "n": n, "candidates": P, "cells": cells, "parallelism": "single GPU"},
         "sw_kernel_gcups": sw_gcups,
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
+        "graph_ms_per_step": graph_ms,
+        "graph_value": cells / (graph_ms / 1e3) / 1e9 if graph_ms else None,
         "gate_2p20": gate,
         "proto_loss": proto,
         "rmt_threshold": rmt,

@@ -22,6 +22,9 @@
 
 namespace subquad {
 
+constexpr int kWeightStride = 8;  // floats per hidden unit of the LDS weight table
+constexpr int kGateMaxH = 256;
+
 struct GateIn {
     const float *emb;
     int64_t n;
@@ -43,37 +46,68 @@ __global__ void gate_node_pack_kernel(const int32_t *__restrict__ self, const in
         node[k] = make_int4(self[k], lens[k], vgene[k], label ? label[k] : 0);
 }
 
-// One pair's inputs as loaded by a group: the rows, the integer features and e_j.
+// The MLP's weights in LDS, kWeightStride floats per hidden unit (W1 row, b1, w2, two
+// spare), so that the gather kernels keep their registers for loads in flight.  The whole
+// block calls it.
+__device__ __forceinline__ void stage_weights(const GateIn &in, float *wsh) {
+    for (int e = threadIdx.x; e < in.H; e += blockDim.x) {
+        float *r = wsh + e * kWeightStride;
+        r[0] = in.W1[e * 4 + 0];
+        r[1] = in.W1[e * 4 + 1];
+        r[2] = in.W1[e * 4 + 2];
+        r[3] = in.W1[e * 4 + 3];
+        r[4] = in.b1[e];
+        r[5] = in.w2[e];
+        r[6] = 0.f;
+        r[7] = 0.f;
+    }
+    __syncthreads();
+}
+
+// One pair's inputs as loaded by a group, before any of them is used: the partner row e_j,
+// the partner's node record and the pair's alignment score.  Loading is branch-free (an
+// out-of-range pair loads node 0 and row 0), so a batch's loads are all in flight together.
 template <int NV>
 struct PairLoad {
-    int64_t p, i, j;  // i < 0: no pair (past the chunk, or out of range)
-    float s, x2, x3;
-    bool same_label;  // packed records only
+    int32_t p, i, j;  // i < 0: no pair (past the chunk, or out of range); p < 2^32 is validated
+    int4 nj;          // (self score, length, V-gene, label) of j (label 0 without packed records)
+    int32_t al;
     float4 ej[NV];
 };
+
+// Node record of k: the packed one, or assembled from the separate arrays.
+__device__ __forceinline__ int4 node_record(const GateIn &in, int64_t k) {
+    return in.node ? in.node[k] : make_int4(in.self[k], in.lens[k], in.vgene[k], 0);
+}
 
 template <int NV>
 __device__ __forceinline__ void load_pair(const GateIn &in, int64_t p, int64_t i, int64_t j, int d4, int l,
                                           PairLoad<NV> &pl) {
-    pl.p = p;
+    pl.p = (int32_t)p;
     const bool ok = p >= 0 && i >= 0 && j >= 0 && i < in.n && j < in.n;
-    pl.i = ok ? i : -1;
-    pl.j = ok ? j : -1;
-    if (!ok) return;
-    if (in.node) {
-        const int4 a = in.node[i], b = in.node[j];
-        pl.s = (float)in.align[p] / sqrtf((float)a.x * (float)b.x);
-        pl.x2 = fabsf((float)(a.y - b.y));
-        pl.x3 = a.z == b.z ? 1.f : 0.f;
-        pl.same_label = a.w == b.w;
-    } else {
-        const float si = (float)in.self[i], sj = (float)in.self[j];
-        pl.s = (float)in.align[p] / sqrtf(si * sj);
-        pl.x2 = fabsf((float)(in.lens[i] - in.lens[j]));
-        pl.x3 = in.vgene[i] == in.vgene[j] ? 1.f : 0.f;
-        pl.same_label = false;
-    }
-    load_row<NV>(in.emb, j, d4, l, pl.ej);
+    pl.i = ok ? (int32_t)i : -1;
+    pl.j = ok ? (int32_t)j : -1;
+    if (in.n == 0) return;  // no row to stand in (every pair is out of range)
+    const int64_t js = ok ? j : 0, ps = ok ? p : 0;
+    pl.nj = node_record(in, js);
+    pl.al = in.align[ps];
+    load_row<NV>(in.emb, js, d4, l, pl.ej);
+}
+
+// The pair's integer features: s = A / sqrt(S_i S_j), |L_i - L_j|, [V_i = V_j], same label.
+struct PairFeat {
+    float s, x2, x3;
+    bool same_label;
+};
+
+template <int NV>
+__device__ __forceinline__ PairFeat pair_features(const PairLoad<NV> &pl, int4 ni) {
+    PairFeat f;
+    f.s = (float)pl.al / sqrtf((float)ni.x * (float)pl.nj.x);
+    f.x2 = fabsf((float)(ni.y - pl.nj.y));
+    f.x3 = ni.z == pl.nj.z ? 1.f : 0.f;
+    f.same_label = ni.w == pl.nj.w;
+    return f;
 }
 
 // Pre-activation of one hidden unit as one fixed fma chain, so that every kernel that
@@ -93,8 +127,8 @@ struct PairState {
 
 template <int NV, int UNITS>
 __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, const PairLoad<NV> &pl,
-                                             const float (&W1)[UNITS][4], const float (&b1)[UNITS],
-                                             const float (&w2)[UNITS], float b2, PairState<UNITS> &st) {
+                                             const PairFeat &ft, const float *wsh, int l, float b2,
+                                             PairState<UNITS> &st) {
     float dot = 0.f, nj2 = 0.f;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -111,8 +145,11 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
     float part = 0.f;
 #pragma unroll
     for (int k = 0; k < UNITS; ++k) {
-        st.z[k] = unit_preact(W1[k], b1[k], pl.s, st.c, pl.x2, pl.x3);
-        part += w2[k] * fmaxf(st.z[k], 0.f);
+        const float *r = wsh + (l + kGroup * k) * kWeightStride;
+        const float4 w = *reinterpret_cast<const float4 *>(r);
+        const float wv[4] = {w.x, w.y, w.z, w.w};
+        st.z[k] = unit_preact(wv, r[4], ft.s, st.c, ft.x2, ft.x3);
+        part += r[5] * fmaxf(st.z[k], 0.f);
     }
     st.u = group_sum(part) + b2;
     st.g = 1.f / (1.f + expf(-st.u));
@@ -150,12 +187,14 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
     const int64_t chunk = ceil_div(in.P, ngroups);
     const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
+    stage_weights(in, wsh);
     if (p0 >= p1) return;
     const int d4 = in.d >> 2;
-    float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
-    load_weights<UNITS>(in, l, W1, b1, w2, b2);
+    const float b2 = in.b2[0];
     float4 ei[NV];
     float ni2 = 0.f;
+    int4 ni = make_int4(0, 0, 0, 0);
     int64_t cur_i = -1;
     for (int64_t p = p0; p < p1; p += kGateBatch) {
         int64_t ib[kGateBatch], jb[kGateBatch];
@@ -178,13 +217,15 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
                 continue;
             }
             if (pl[u].i != cur_i) {
+                ni = node_record(in, pl[u].i);
                 load_row_norm<NV>(in, pl[u].i, d4, l, ei, ni2);
                 cur_i = pl[u].i;
             }
+            const PairFeat ft = pair_features<NV>(pl[u], ni);
             PairState<UNITS> st;
-            pair_forward<NV, UNITS>(ei, ni2, pl[u], W1, b1, w2, b2, st);
+            pair_forward<NV, UNITS>(ei, ni2, pl[u], ft, wsh, l, b2, st);
             if (l == 0) {
-                fused[p + u] = st.g * pl[u].s + st.gm * st.c;
+                fused[p + u] = st.g * ft.s + st.gm * st.c;
                 if (gate) gate[p + u] = st.g;
             }
         }
@@ -202,15 +243,21 @@ struct TrainOut {
 };
 
 
-// First pass of the backward, over the pairs in order of their first index i (order_i):
+// First pass of the backward, over the pairs in order of their first index i (order_i: the
+// records (i << 32 | p) sorted, or in their natural order when the pairs are sorted already):
 // recomputes the forward, accumulates e_i's gradient in registers over its row, and stores
 // per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
 // feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
 template <int NV, int UNITS, bool TRAIN>
 __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
-                                                                const uint64_t *__restrict__ order_i,
+                                                                const uint64_t *__restrict__ order_nat,
+                                                                const uint64_t *__restrict__ order_sorted,
+                                                                const int64_t *__restrict__ unsorted,
                                                                 float4 *__restrict__ pack, float4 *__restrict__ feat,
                                                                 float *__restrict__ demb, TrainOut tr) {
+    // Pairs already in order of i (the candidate lists are): walk them as they are, p = q.
+    const bool natural = unsorted[0] == 0;
+    const uint64_t *__restrict__ order_i = natural ? order_nat : order_sorted;
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
@@ -218,18 +265,21 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
     double loss_acc = 0.0;
     const int d4 = in.d >> 2;
-    float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
-    load_weights<UNITS>(in, l, W1, b1, w2, b2);
+    __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
+    stage_weights(in, wsh);
+    const float b2 = in.b2[0];
     float4 ei[NV], gi[NV], old[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
     float ni2 = 0.f;
+    int4 ni = make_int4(0, 0, 0, 0);
     int64_t cur_i = -1;
     bool started_here = false;
     for (int64_t q = q0; q < q1; q += kGateBatch) {
         int64_t pb[kGateBatch], ib[kGateBatch], jb[kGateBatch];
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) pb[u] = q + u < q1 ? (int64_t)(uint32_t)order_i[q + u] : -1;
+        for (int u = 0; u < kGateBatch; ++u)
+            pb[u] = q + u < q1 ? (natural ? q + u : (int64_t)(uint32_t)order_i[q + u]) : -1;
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
             ib[u] = pb[u] >= 0 ? in.pairs[2 * pb[u]] : -1;
@@ -261,15 +311,17 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
                 if (demb) load_grad_row<NV>(demb, i, d4, l, old);
+                ni = node_record(in, i);
                 load_row_norm<NV>(in, i, d4, l, ei, ni2);
             }
+            const PairFeat ft = pair_features<NV>(pl[u], ni);
             PairState<UNITS> st;
-            pair_forward<NV, UNITS>(ei, ni2, pl[u], W1, b1, w2, b2, st);
+            pair_forward<NV, UNITS>(ei, ni2, pl[u], ft, wsh, l, b2, st);
             float gf;
             if (TRAIN) {
-                const float f = st.g * pl[u].s + st.gm * st.c;
+                const float f = st.g * ft.s + st.gm * st.c;
                 float lp;
-                if (pl[u].same_label) {
+                if (ft.same_label) {
                     const float e = 1.f - f;
                     lp = e * e;
                     gf = -2.f * e * tr.inv_P;
@@ -285,15 +337,18 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             } else {
                 gf = gfb[u];
             }
-            const float ubar = gf * (pl[u].s - st.c) * st.g * st.gm;
+            const float ubar = gf * (ft.s - st.c) * st.g * st.gm;
             float xc = 0.f;
 #pragma unroll
-            for (int k = 0; k < UNITS; ++k) xc += st.z[k] > 0.f ? W1[k][1] * w2[k] : 0.f;
+            for (int k = 0; k < UNITS; ++k) {
+                const float *r = wsh + (l + kGroup * k) * kWeightStride;
+                xc += st.z[k] > 0.f ? r[1] * r[5] : 0.f;
+            }
             const float cbar = gf * st.gm + ubar * group_sum(xc);
             const float inv = st.ok ? 1.f / (st.ni * st.nj) : 0.f;
             if (l == 0) {
                 pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
-                feat[p] = make_float4(pl[u].s, st.c, pl[u].x2, pl[u].x3);
+                feat[p] = make_float4(ft.s, st.c, ft.x2, ft.x3);
             }
             if (demb && st.ok) {
                 const float ci = st.c / (st.ni * st.ni);
@@ -467,9 +522,17 @@ static int gate_fwd_nv(const GateIn &in, float *fused, float *gate, hipStream_t 
     return SUBQUAD_OK;
 }
 
+struct GateOrders {
+    const uint64_t *order_nat;  // (i << 32 | p) in natural order
+    const uint64_t *order_i;    // the same sorted by i (meaningful only when unsorted[0] != 0)
+    const uint64_t *order_j;    // (j << 32 | p) sorted by j
+    const int64_t *unsorted;    // [0]: 1 when the pairs are not in order of i, [1]: records the i sort takes
+};
+
 template <int NV, bool TRAIN>
-static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, int64_t *lblocks, const uint64_t *order_i,
-                       const uint64_t *order_j, float4 *pack, float4 *feat, float *demb, double *wacc, hipStream_t st) {
+static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, int64_t *lblocks, const GateOrders &o,
+                       float4 *pack, float4 *feat, float *demb, double *wacc, hipStream_t st) {
+    const uint64_t *order_j = o.order_j;
     switch (in.H / kGroup) {
 #define SQ_CASE(U)                                                                                                 \
     case U: {                                                                                                      \
@@ -477,8 +540,8 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
             const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U, TRAIN>);                 \
             if (lblocks) *lblocks = blocks;                                                                        \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
-            gate_bwd_kernel<NV, U, TRAIN><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, order_i, pack, feat,  \
-                                                                                    demb, tr);                     \
+            gate_bwd_kernel<NV, U, TRAIN><<<(unsigned)blocks, kGateThreads, 0, st>>>(                                \
+                in, gf, o.order_nat, o.order_i, o.unsorted, pack, feat, demb, tr);                                \
         }                                                                                                          \
         SQ_LAUNCHED("gate_bwd_kernel");                                                                            \
         {                                                                                                          \
@@ -509,7 +572,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
 static int64_t gate_max_blocks() { return (int64_t)device_cus() * 8; }
 
 struct GateBwdLayout {
-    size_t wacc, ra, rb, rc, rd, pack, feat, node, lpart, radix, total;
+    size_t wacc, ra, rb, rc, rd, pack, feat, node, lpart, flags, radix, total;
 };
 
 static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
@@ -525,28 +588,64 @@ static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
     L.feat = take(sizeof(float4) * P);
     L.node = take(sizeof(int4) * n);
     L.lpart = take(sizeof(double) * (size_t)gate_max_blocks());
+    L.flags = take(sizeof(int64_t) * 2);
     L.radix = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
     L.total = off;
     return L;
 }
 
-// Sorts the pair indices by their first and by their second index (stable, so each row
-// keeps the input order) for the two backward passes.
+// flags[0] = 1 when some pair's i key (n for an out-of-range pair) exceeds the next one's.
+__global__ void gate_sorted_init_kernel(int64_t *__restrict__ flags) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0;
+}
+
+__global__ void gate_sorted_check_kernel(const int32_t *__restrict__ pairs, int64_t P, int64_t n,
+                                         int64_t *__restrict__ flags) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p + 1 < P; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t a = pairs[2 * p], b = pairs[2 * p + 2];
+        const int64_t ka = (a < 0 || a >= n || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= n) ? n : a;
+        const int64_t kb = (b < 0 || b >= n || pairs[2 * p + 3] < 0 || pairs[2 * p + 3] >= n) ? n : b;
+        if (ka > kb) flags[0] = 1;  // every writer stores the same value
+    }
+}
+
+// flags[1] = records the sort by i takes: P when the pairs are out of order, else none.
+__global__ void gate_sorted_count_kernel(int64_t *__restrict__ flags, int64_t P) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[1] = flags[0] ? P : 0;
+}
+
+// Orders of the pair indices by their first and by their second index (stable, so each row
+// keeps the input order) for the two backward passes.  When the pairs already come in order
+// of i (the candidate lists do), the i sort is given no records and the first pass walks the
+// pairs as they are.
 static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws, const GateBwdLayout &L,
-                            hipStream_t st, uint64_t **order_i, uint64_t **order_j) {
+                            hipStream_t st, GateOrders &o) {
     uint64_t *ra = reinterpret_cast<uint64_t *>(ws + L.ra), *rb = reinterpret_cast<uint64_t *>(ws + L.rb);
     uint64_t *rc = reinterpret_cast<uint64_t *>(ws + L.rc), *rd = reinterpret_cast<uint64_t *>(ws + L.rd);
+    int64_t *flags = reinterpret_cast<int64_t *>(ws + L.flags);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 16);
     const int bits = key_bits_for(n);
+    gate_sorted_init_kernel<<<1, 64, 0, st>>>(flags);
+    SQ_LAUNCHED("gate_sorted_init_kernel");
+    gate_sorted_check_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, flags);
+    SQ_LAUNCHED("gate_sorted_check_kernel");
+    gate_sorted_count_kernel<<<1, 64, 0, st>>>(flags, P);
+    SQ_LAUNCHED("gate_sorted_count_kernel");
     gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 0, ra);
     SQ_LAUNCHED("gate_order_keys_kernel");
-    int rc_ = radix_sort_u64(ra, rb, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, order_i, "sort_gate_i");
+    // With no records to sort (pairs already in order) the sort writes nothing and ra keeps
+    // the natural order, which is then the one used; otherwise its result is.
+    uint64_t *order_i = nullptr, *order_j = nullptr;
+    int rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, L.total - L.radix, st, &order_i,
+                             "sort_gate_i");
     if (rc_ != SUBQUAD_OK) return rc_;
     gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 1, rc);
     SQ_LAUNCHED("gate_order_keys_kernel");
-    return radix_sort_u64(rc, rd, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, order_j, "sort_gate_j");
+    rc_ = radix_sort_u64(rc, rd, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, &order_j, "sort_gate_j");
+    if (rc_ != SUBQUAD_OK) return rc_;
+    o = GateOrders{ra, order_i, order_j, flags};
+    return SUBQUAD_OK;
 }
-
 
 // ------------------------------------------------------------------ training signal
 
@@ -676,19 +775,19 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
         SQ_LAUNCHED("gate_node_pack_kernel");
     }
     in.node = node;
-    uint64_t *order_i = nullptr, *order_j = nullptr;
-    rc = gate_pair_orders(in.pairs, in.P, in.n, w, L, st, &order_i, &order_j);
+    GateOrders orders{};
+    rc = gate_pair_orders(in.pairs, in.P, in.n, w, L, st, orders);
     if (rc != SUBQUAD_OK) return rc;
     float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
     float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
     const TrainOut tr{margin, 1.f / (float)in.P, fused, lpart};
     int64_t lblocks = 0;
     const int nv = (int)ceil_div(in.d / 4, kGroup);
-    if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 2) rc = gate_bwd_nv<2, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 4) rc = gate_bwd_nv<4, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
-    else if (nv <= 8) rc = gate_bwd_nv<8, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
-    else rc = gate_bwd_nv<16, TRAIN>(in, grad_fused, tr, &lblocks, order_i, order_j, pack, feat, demb, wacc, st);
+    if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
+    else rc = gate_bwd_nv<16, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
     if (rc != SUBQUAD_OK) return rc;
     gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, in.H, dW1, db1, dw2, db2);
     SQ_LAUNCHED("gate_ws_finish_kernel");

@@ -296,3 +296,27 @@ def test_gate_train_empty():
     fused, loss, grads = sq.api.gate_train(*gpu_args(c), dev(rep.family.astype(np.int32)), 0.5)
     torch.cuda.synchronize()
     assert fused.shape == (0,) and loss.item() == 0.0 and not grads[4].any()
+
+
+def test_backward_sorted_and_shuffled_pairs_agree():
+    """Pairs already in order of i take the backward's natural-order path (no i sort); the
+    same pairs shuffled take the sorted path: gradients agree to summation order, and both
+    match the oracle."""
+    rep = synth.tiny(n_families=60, fam_size=8, seed=41)
+    c = make_case(rep, 128, 64, 5000, seed=41)
+    order = np.lexsort((c["pairs"][:, 1], c["pairs"][:, 0]))
+    cs = dict(c, pairs=np.ascontiguousarray(c["pairs"][order]), align=np.ascontiguousarray(c["align"][order]))
+    cs, amb = split_ambiguous(cs)
+    gf = synth.upstream_grad(cs["pairs"].shape[0], seed=41)
+    perm = np.random.default_rng(41).permutation(cs["pairs"].shape[0])
+    cu = dict(cs, pairs=np.ascontiguousarray(cs["pairs"][perm]), align=np.ascontiguousarray(cs["align"][perm]))
+    say(f"gate bwd sorted vs shuffled pairs (P={cs['pairs'].shape[0]})")
+    g_sorted = sq.gate_bwd(*gpu_args(cs), dev(gf))
+    g_shuf = sq.gate_bwd(*gpu_args(cu), dev(gf[perm]))
+    torch.cuda.synchronize()
+    ref = ogate.backward(**oracle_args(cs), grad_f=gf)
+    for name, a, b in zip(("W1", "b1", "w2", "b2", "emb"), g_sorted, g_shuf):
+        for g in (a, b):
+            ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
+            assert ok, (name, rel)
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(b.abs().max()))
