@@ -479,7 +479,8 @@ def main():
         # e_i's gradient, rows by j write e_j's
         "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 20 + d * 4)),
         "gate_cos_bwd_j_kernel": ("hbm", P * d * 4),
-        "sort_gate_i_scatter": ("hbm", 2 * P * 8),
+        # (the i-order sort has no roofline entry: the candidate pairs arrive in order of i,
+        # so its device-side record count is zero and its launches return at once)
         "sort_gate_j_scatter": ("hbm", 2 * P * 8),
         "sort_lengths_scatter": ("hbm", 2 * P * 8),
         "align_kernel": ("alu", cells * SW_OPS_PER_CELL),

@@ -5,11 +5,13 @@
 // A pair (i, j), i < j, of one repertoire is a candidate iff for some band beta the r-tuples
 // sig[i][beta*r .. beta*r + r) and sig[j][...] are exactly equal.  Steps:
 //   1. band records: for every (beta, i) a 64-bit mix of (tuple, repertoire); the record is
-//      (top 32 bits of the mix) << 32 | (beta * n + i), written band-major.  An 8-bit
+//      (top bits of the mix | beta) << 32 | (beta * n + i), written band-major (beta in the
+//      word's low bits when the sort key leaves them free).  An 8-bit
 //      fingerprint of every (i, beta) mix goes to a row-major table F[n][b].
-//   2. stable radix sort of the records on their top 32 bits.  Stability keeps records with
-//      equal mix bits in (beta, i) order, so each bucket (equal mix bits, equal band) is a
-//      contiguous run with ascending i.
+//   2. stable radix sort of the records on their mix bits (log2 n + 4 rounded up to whole
+//      bytes, at most 32: 24 for n <= 2^20; the bits below are cleared).  Stability keeps
+//      records with equal mix bits in (beta, i) order, so each bucket (equal mix bits, equal
+//      band) is a contiguous run with ascending i.
 //   3. run scan: for every record, every later record of its run is a potential partner.
 //      The pair is kept only if (a) both rows are in one repertoire, (b) the band tuples are
 //      exactly equal, and (c) beta is the FIRST band in which the tuples are equal (earlier
@@ -25,6 +27,7 @@ namespace subquad {
 
 constexpr int kKeysTileSeqs = 64;
 constexpr int kKeysThreads = 256;
+constexpr int kKeysUnroll = 8;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 33)) * 0xFF51AFD7ED558CCDull;
@@ -36,20 +39,41 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 // (item e = s * b + beta), record stores are contiguous per band (staged through LDS).
 __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     const uint64_t *__restrict__ sig, int64_t n, int32_t M, int32_t b, int32_t r,
-    const int64_t *__restrict__ offs, int64_t R, uint64_t *__restrict__ rec, uint8_t *__restrict__ F) {
+    const int64_t *__restrict__ offs, int64_t R, uint32_t keep, uint32_t band_in_key, uint64_t *__restrict__ rec,
+    uint8_t *__restrict__ F) {
     extern __shared__ uint32_t keyhi[];  // [b][64]
     const int64_t i0 = (int64_t)blockIdx.x * kKeysTileSeqs;
     const int items = kKeysTileSeqs * b;
-    for (int e = threadIdx.x; e < items; e += blockDim.x) {
-        int s = e / b, beta = e - s * b;
-        int64_t i = i0 + s;
-        if (i >= n) continue;
-        const uint64_t *tup = sig + i * (int64_t)M + (int64_t)beta * r;
-        uint64_t rep = R > 1 ? (uint64_t)rep_of(offs, R, i) : 0ull;
-        uint64_t h = mix64(rep * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull + (uint64_t)beta);
-        for (int k = 0; k < r; ++k) h = mix64(h ^ tup[k]);
-        keyhi[beta * kKeysTileSeqs + s] = (uint32_t)(h >> 32);
-        F[i * b + beta] = (uint8_t)h;
+    // kKeysUnroll items per thread at a time, so that their signature loads are in flight
+    // together
+    for (int e0 = 0; e0 < items; e0 += kKeysThreads * kKeysUnroll) {
+        uint64_t h[kKeysUnroll];
+        const uint64_t *tup[kKeysUnroll];
+#pragma unroll
+        for (int u = 0; u < kKeysUnroll; ++u) {
+            const int e = e0 + u * kKeysThreads + threadIdx.x;
+            const int s = e / b, beta = e - s * b;
+            const int64_t i = i0 + s;
+            const bool ok = e < items && i < n;
+            tup[u] = ok ? sig + i * (int64_t)M + (int64_t)beta * r : nullptr;
+            const uint64_t rep = ok && R > 1 ? (uint64_t)rep_of(offs, R, i) : 0ull;
+            h[u] = mix64(rep * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull + (uint64_t)beta);
+        }
+        for (int k = 0; k < r; ++k) {
+            uint64_t w[kKeysUnroll];
+#pragma unroll
+            for (int u = 0; u < kKeysUnroll; ++u) w[u] = tup[u] ? tup[u][k] : 0ull;
+#pragma unroll
+            for (int u = 0; u < kKeysUnroll; ++u) h[u] = mix64(h[u] ^ w[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kKeysUnroll; ++u) {
+            if (!tup[u]) continue;
+            const int e = e0 + u * kKeysThreads + threadIdx.x;
+            const int s = e / b, beta = e - s * b;
+            keyhi[beta * kKeysTileSeqs + s] = ((uint32_t)(h[u] >> 32) & keep) | (band_in_key ? (uint32_t)beta : 0u);
+            F[(i0 + s) * b + beta] = (uint8_t)h[u];
+        }
     }
     __syncthreads();
     for (int e = threadIdx.x; e < items; e += blockDim.x) {
@@ -61,9 +85,20 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     }
 }
 
+// Number of mix bits (a multiple of 8, at most 32) that the record sort orders by.
+static int record_mix_bits(int64_t n) {
+    int lg = 0;
+    while ((int64_t(1) << lg) < n) ++lg;
+    return std::min(32, (int)ceil_div(lg + 4, 8) * 8);
+}
+
 // Step 3a.  Runs: a record that starts a run of >= 2 records (equal mix bits, equal band)
 // appends (start << 32 | length) to the run list and adds its pair count.
+// BAND_IN_KEY: bits 32.. of a record hold its band as well as its mix bits (the sort key
+// leaves them room), so no division is needed.
+template <bool BAND_IN_KEY>
 __device__ __forceinline__ bool same_bucket(uint64_t a, uint64_t c, uint32_t n32) {
+    if (BAND_IN_KEY) return (a >> 32) == (c >> 32);
     return (a >> 32) == (c >> 32) && ((uint32_t)a / n32) == ((uint32_t)c / n32);
 }
 
@@ -72,13 +107,14 @@ constexpr int kRunsItems = 16;
 constexpr int kRunsTile = kRunsThreads * kRunsItems;
 constexpr int kSmallRun = 8;  // runs up to this many records: all their pairs in one thread
 
-// Length of the run starting at q (srec[q + 1] is known to be in it): the bucket's records
-// are contiguous, so gallop forward, then bisect: O(log m) loads for a run of m records.
-__device__ __forceinline__ int64_t run_length(const uint64_t *__restrict__ srec, int64_t total, int64_t q, uint32_t n32) {
-    const uint64_t me = srec[q];
-    int64_t good = q + 1, bad = total, stride = 1;
-    while (good + stride < total) {
-        if (!same_bucket(srec[good + stride], me, n32)) {
+// End of a bucket's run in sorted records: `good` is known to be in the run whose record
+// is `me`, and a bucket's records are contiguous, so gallop forward, then bisect: O(log m)
+// loads.  Returns the first index past the run (at most `end`).  `at(x)` reads record x.
+template <bool BAND_IN_KEY, typename At>
+__device__ __forceinline__ int64_t run_end(At at, int64_t good, int64_t end, uint64_t me, uint32_t n32) {
+    int64_t bad = end, stride = 1;
+    while (good + stride < end) {
+        if (!same_bucket<BAND_IN_KEY>(at(good + stride), me, n32)) {
             bad = good + stride;
             break;
         }
@@ -87,78 +123,144 @@ __device__ __forceinline__ int64_t run_length(const uint64_t *__restrict__ srec,
     }
     while (bad - good > 1) {
         const int64_t mid = good + ((bad - good) >> 1);
-        if (same_bucket(srec[mid], me, n32)) good = mid;
+        if (same_bucket<BAND_IN_KEY>(at(mid), me, n32)) good = mid;
         else bad = mid;
     }
-    return bad - q;
+    return bad;
 }
 
-// A block takes tiles of kRunsTile sorted records, kRunsItems consecutive ones per thread:
-// pass 1 counts the run starts, a block scan gives each thread its slots and one atomic per
-// block reserves them, pass 2 measures the runs.  Runs of at most kSmallRun records go to
-// `runs` (in record order: one thread will walk all their pairs); longer ones, few, go to
-// `bruns` with their pair counts in `bpcount` (their pairs are spread over threads).
-// counters: [0] small runs, [1] pairs of the long runs, [2] long runs.
+// Per tile of kRunsTile sorted records: room for its run starts (at most kRunsTile / 2,
+// since a run has >= 2 records) from the front, and for its long runs (each starts at least
+// kSmallRun + 1 records after the previous one) from the back.
+constexpr int kRunsCap = kRunsTile / 2 + kRunsTile / (kSmallRun + 1) + 1;
+
+// A block takes tiles of kRunsTile sorted records; thread t holds records t, t + 256, ...
+// of the tile in registers (so a wave's neighbour reads in LDS are consecutive words).
+// Pass 1 marks the run starts and a block scan gives each thread its slots in the tile's
+// region; pass 2 measures the runs.  Every run start takes a slot at the front: its record
+// (start << 32 | length) when the run has at most kSmallRun records (one thread will walk
+// all its pairs), else an empty record (length 0), the run itself going to the back of the
+// region (its pairs are spread over threads).  No global atomics: the tile writes its
+// counts, tmeta[tile] = (starts, long runs), tcount[tile] = starts | long runs << 32 and
+// tpairs[tile] = pairs of its long runs, which a scan over tiles turns into list offsets.
+template <bool BAND_IN_KEY>
 __global__ __launch_bounds__(kRunsThreads) void lsh_runs_kernel(const uint64_t *__restrict__ srec, int64_t total,
-                                                                int64_t n, uint64_t *__restrict__ runs,
-                                                                uint64_t *__restrict__ bruns,
-                                                                uint64_t *__restrict__ bpcount,
-                                                                unsigned long long *__restrict__ counters) {
+                                                                int64_t n, uint64_t *__restrict__ region,
+                                                                uint2 *__restrict__ tmeta,
+                                                                uint64_t *__restrict__ tcount,
+                                                                uint64_t *__restrict__ tpairs) {
     const uint32_t n32 = (uint32_t)n;
+    const int t = threadIdx.x;
     __shared__ uint32_t scan[kRunsThreads];
-    __shared__ unsigned long long base_sh;
+    __shared__ uint32_t nlong;
+    __shared__ unsigned long long lpairs;
     __shared__ uint64_t tile_sh[kRunsTile + 2];  // records tile-1 .. tile+kRunsTile
     for (int64_t tile = (int64_t)blockIdx.x * kRunsTile; tile < total; tile += (int64_t)gridDim.x * kRunsTile) {
-        // coalesced staging of the tile and its two neighbours (absent ones read as ~0)
-        for (int e = threadIdx.x; e < kRunsTile + 2; e += kRunsThreads) {
-            const int64_t q = tile - 1 + e;
-            tile_sh[e] = q >= 0 && q < total ? srec[q] : ~0ull;
+        const int64_t ti = tile / kRunsTile;
+        uint64_t *reg = region + ti * kRunsCap;
+        // the tile's loads all issue before any is used (absent records read as ~0)
+        uint64_t v[kRunsItems];
+#pragma unroll
+        for (int k = 0; k < kRunsItems; ++k) {
+            const int64_t q = tile + k * kRunsThreads + t;
+            v[k] = q < total ? srec[q] : ~0ull;
         }
+        if (t < 2) {
+            const int64_t q = t == 0 ? tile - 1 : tile + kRunsTile;
+            tile_sh[t == 0 ? 0 : kRunsTile + 1] = q >= 0 && q < total ? srec[q] : ~0ull;
+        }
+        if (t == 0) {
+            nlong = 0u;
+            lpairs = 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < kRunsItems; ++k) tile_sh[1 + k * kRunsThreads + t] = v[k];
         __syncthreads();
-        const int64_t q0 = tile + (int64_t)threadIdx.x * kRunsItems;
-        const uint64_t *ts = tile_sh + 1 + threadIdx.x * kRunsItems;  // ts[k] = srec[q0 + k]
         // run starts of >= 2 records among this thread's items: bit k for item k
         uint32_t starts = 0;
 #pragma unroll
         for (int k = 0; k < kRunsItems; ++k) {
-            const int64_t q = q0 + k;
-            if (q + 1 >= total) break;  // the last record starts no run of two
-            const uint64_t me = ts[k];
-            const bool start = q == 0 || !same_bucket(ts[k - 1], me, n32);
-            if (start && same_bucket(ts[k + 1], me, n32)) starts |= 1u << k;
+            const int e = k * kRunsThreads + t;  // place in the tile
+            const int64_t q = tile + e;
+            if (q + 1 < total) {  // the last record starts no run of two
+                const bool start = q == 0 || !same_bucket<BAND_IN_KEY>(tile_sh[e], v[k], n32);
+                if (start && same_bucket<BAND_IN_KEY>(tile_sh[e + 2], v[k], n32)) starts |= 1u << k;
+            }
         }
         const uint32_t cnt = __builtin_popcount(starts);
-        scan[threadIdx.x] = cnt;
+        scan[t] = cnt;
         __syncthreads();
         for (int off = 1; off < kRunsThreads; off <<= 1) {  // inclusive scan
-            const uint32_t v = threadIdx.x >= off ? scan[threadIdx.x - off] : 0u;
+            const uint32_t x = t >= off ? scan[t - off] : 0u;
             __syncthreads();
-            scan[threadIdx.x] += v;
+            scan[t] += x;
             __syncthreads();
         }
-        if (threadIdx.x == kRunsThreads - 1)
-            base_sh = scan[threadIdx.x] ? atomicAdd(&counters[0], (unsigned long long)scan[threadIdx.x]) : 0ull;
-        __syncthreads();
-        unsigned long long slot = base_sh + scan[threadIdx.x] - cnt;
+        uint32_t slot = scan[t] - cnt;
         while (starts) {
             const int k = __builtin_ctz(starts);
             starts &= starts - 1;
-            const int64_t q = q0 + k;
-            const int64_t m = run_length(srec, total, q, n32);
+            const int e0 = k * kRunsThreads + t;
+            const int64_t q = tile + e0;
+            // the run is measured in the staged tile; only one that reaches the tile's end
+            // goes on in global memory
+            const uint64_t me = tile_sh[1 + e0];
+            const int64_t tend = min<int64_t>(kRunsTile, total - tile);  // records in the tile
+            int64_t end = run_end<BAND_IN_KEY>([&](int64_t x) { return tile_sh[1 + x]; }, e0 + 1, tend, me, n32);
+            if (end == tend && tile + tend < total)
+                end = run_end<BAND_IN_KEY>([&](int64_t x) { return srec[x]; }, tile + tend - 1, total, me, n32) - tile;
+            const int64_t m = end - e0;
             const uint64_t rec = ((uint64_t)q << 32) | (uint64_t)m;
             if (m <= kSmallRun) {
-                runs[slot] = rec;
-            } else {  // a long run: rare, one atomic each
-                runs[slot] = 0;  // an empty small run (m = 0) keeps the slot list dense
-                const unsigned long long b = atomicAdd(&counters[2], 1ull);
-                bruns[b] = rec;
-                const uint64_t c = (uint64_t)m * (uint64_t)(m - 1) / 2;
-                bpcount[b] = c;
-                atomicAdd(&counters[1], (unsigned long long)c);
+                reg[slot] = rec;
+            } else {
+                reg[slot] = 0ull;
+                const uint32_t l = atomicAdd(&nlong, 1u);
+                reg[kRunsCap - 1 - l] = rec;
+                atomicAdd(&lpairs, (unsigned long long)((uint64_t)m * (uint64_t)(m - 1) / 2));
             }
             ++slot;
         }
-        __syncthreads();  // scan and base_sh are reused by the next tile
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t ns = scan[kRunsThreads - 1];
+            tmeta[ti] = make_uint2(ns, nlong);
+            tcount[ti] = (uint64_t)ns | ((uint64_t)nlong << 32);
+            tpairs[ti] = lpairs;
+        }
+        __syncthreads();  // scan, the LDS counters and the tile are reused by the next tile
+    }
+}
+
+// After the scan over tiles (tcount, tpairs exclusive): tile ti's run starts go to
+// runs[starts before ti ...], its long runs to bruns[long runs before ti ...] with their
+// first flattened pair index in bpoff.  The last tile publishes the totals: counters [0] run
+// starts, [1] pairs of the long runs, [2] long runs.
+__global__ __launch_bounds__(kRunsThreads) void lsh_compact_kernel(
+    const uint64_t *__restrict__ region, const uint2 *__restrict__ tmeta, const uint64_t *__restrict__ tcount,
+    const uint64_t *__restrict__ tpairs, int64_t T, uint64_t *__restrict__ runs, uint64_t *__restrict__ bruns,
+    uint64_t *__restrict__ bpoff, unsigned long long *__restrict__ counters) {
+    for (int64_t ti = blockIdx.x; ti < T; ti += gridDim.x) {
+        const uint2 meta = tmeta[ti];
+        const uint64_t base = tcount[ti];
+        const uint64_t sbase = base & 0xFFFFFFFFull, lbase = base >> 32;
+        const uint64_t *reg = region + ti * kRunsCap;
+        for (uint32_t x = threadIdx.x; x < meta.x; x += kRunsThreads) runs[sbase + x] = reg[x];
+        if (threadIdx.x == 0) {
+            uint64_t acc = tpairs[ti];
+            for (uint32_t l = 0; l < meta.y; ++l) {
+                const uint64_t rec = reg[kRunsCap - 1 - l];
+                const uint64_t m = rec & 0xFFFFFFFFull;
+                bruns[lbase + l] = rec;
+                bpoff[lbase + l] = acc;
+                acc += m * (m - 1) / 2;
+            }
+            if (ti == T - 1) {
+                counters[0] = sbase + meta.x;
+                counters[1] = acc;
+                counters[2] = lbase + meta.y;
+            }
+        }
     }
 }
 
@@ -373,6 +475,10 @@ static int bits_for(int64_t n) {
     return nb;
 }
 
+static int64_t runs_tiles(int64_t recs) { return ceil_div(recs, kRunsTile); }
+// long runs (>= kSmallRun + 1 records each) in `recs` records
+static int64_t long_cap(int64_t recs) { return recs / (kSmallRun + 1) + 1; }
+
 static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
     LshLayout L{};
     const int64_t recs = n * b;
@@ -381,12 +487,13 @@ static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
     L.rec_a = take(sizeof(uint64_t) * recs);
     L.rec_b = take(sizeof(uint64_t) * recs);
     L.fp = take((size_t)recs);
-    L.runs = take(sizeof(uint64_t) * (recs / 2 + 1));
-    L.poff = take(sizeof(uint64_t) * (recs / 2 + 1));
+    const int64_t T = runs_tiles(recs);
+    L.runs = take(sizeof(uint64_t) * (size_t)T * kRunsCap);
+    L.poff = take(sizeof(uint64_t) * (size_t)(2 * long_cap(recs) + 3 * T));
     L.pk_a = take(sizeof(uint64_t) * cap);
     L.pk_b = take(sizeof(uint64_t) * cap);
     L.misc = take(128);
-    L.radix = take(std::max(radix_scratch_bytes(std::max<int64_t>(recs, cap)), scan64_scratch_bytes(recs / 2 + 1)));
+    L.radix = take(std::max(radix_scratch_bytes(std::max<int64_t>(recs, cap)), scan64_scratch_bytes(T)));
     L.total = off;
     return L;
 }
@@ -421,31 +528,59 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
 
     lsh_init_kernel<<<1, 64, 0, st>>>(count);
     SQ_LAUNCHED("lsh_init_kernel");
+    // Mix bits kept in the sort key: enough that a band's n records rarely share them by
+    // chance (n / 2^bits <= 1/16, each such meeting costing one tuple comparison), in whole
+    // radix digits, so a small repertoire sorts in fewer passes.
+    const int mix_bits = record_mix_bits(n);
+    const uint32_t keep = mix_bits >= 32 ? ~0u : ~((1u << (32 - mix_bits)) - 1u);
+    // the band goes into the cleared bits when they can hold it: runs then compare whole
+    // key words, with no division by n
+    const uint32_t band_in_key = mix_bits <= 24 && b <= 256 ? 1u : 0u;
     const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;
     SQ_REQUIRE(lds <= 64 * 1024, SUBQUAD_ERR_ARG, "too many bands");
     {
         ProfScope prof("lsh_keys_kernel", st);
         lsh_keys_kernel<<<(unsigned)ceil_div(n, kKeysTileSeqs), kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R,
-                                                                                          rec_a, F);
+                                                                                          keep, band_in_key, rec_a, F);
     }
     SQ_LAUNCHED("lsh_keys_kernel");
     uint64_t *sorted = nullptr;
-    int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 32, 32, rscratch, rscratch_bytes, st, &sorted, "sort_records");
+    int rc = radix_sort_u64(rec_a, rec_b, recs, nullptr, 64 - mix_bits, mix_bits, rscratch, rscratch_bytes, st, &sorted,
+                            "sort_records");
     if (rc != SUBQUAD_OK) return rc;
-    uint64_t *runs = reinterpret_cast<uint64_t *>(ws + L.runs);
-    // the long runs (>= kSmallRun + 1 records each, so at most recs / 9 / 2 of them) and
-    // their pair counts share the poff region
-    const int64_t big_cap = recs / (2 * (kSmallRun + 1)) + 1;
+    // per-tile regions, then the compact lists: the run starts in the record buffer the sort
+    // left free, the long runs and their pair offsets in the poff region
+    const int64_t T = runs_tiles(recs);
+    uint64_t *region = reinterpret_cast<uint64_t *>(ws + L.runs);
+    uint64_t *runs = sorted == rec_a ? rec_b : rec_a;
+    const int64_t big_cap = long_cap(recs);
     uint64_t *bruns = reinterpret_cast<uint64_t *>(ws + L.poff);
     uint64_t *bpoff = bruns + big_cap;
-    unsigned long long *counters = count + 2;  // [0] short runs, [1] long-run pairs, [2] long runs
-    {
-        const int64_t grid = std::min<int64_t>(ceil_div(recs, kRunsTile), (int64_t)device_cus() * 8);
-        ProfScope prof("lsh_runs_kernel", st);
-        lsh_runs_kernel<<<(unsigned)std::max<int64_t>(grid, 1), kRunsThreads, 0, st>>>(sorted, recs, n, runs, bruns,
-                                                                                       bpoff, counters);
+    uint64_t *tcount = bpoff + big_cap;
+    uint64_t *tpairs = tcount + T;
+    uint2 *tmeta = reinterpret_cast<uint2 *>(tpairs + T);
+    unsigned long long *counters = count + 2;  // [0] run starts, [1] long-run pairs, [2] long runs
+    if (T > 0) {
+        const unsigned g = (unsigned)std::min<int64_t>(T, (int64_t)device_cus() * 8);
+        {
+            ProfScope prof("lsh_runs_kernel", st);
+            if (band_in_key)
+                lsh_runs_kernel<true><<<g, kRunsThreads, 0, st>>>(sorted, recs, n, region, tmeta, tcount, tpairs);
+            else
+                lsh_runs_kernel<false><<<g, kRunsThreads, 0, st>>>(sorted, recs, n, region, tmeta, tcount, tpairs);
+        }
+        SQ_LAUNCHED("lsh_runs_kernel");
+        rc = scan_exclusive_u64(tcount, T, nullptr, rscratch, st);
+        if (rc != SUBQUAD_OK) return rc;
+        rc = scan_exclusive_u64(tpairs, T, nullptr, rscratch, st);
+        if (rc != SUBQUAD_OK) return rc;
+        {
+            ProfScope prof("lsh_compact_kernel", st);
+            lsh_compact_kernel<<<g, kRunsThreads, 0, st>>>(region, tmeta, tcount, tpairs, T, runs, bruns, bpoff,
+                                                           counters);
+        }
+        SQ_LAUNCHED("lsh_compact_kernel");
     }
-    SQ_LAUNCHED("lsh_runs_kernel");
     {
         ProfScope prof("lsh_emit_small_kernel", st);
         lsh_emit_small_kernel<<<(unsigned)((int64_t)device_cus() * 8), kEmitThreads, 0, st>>>(
@@ -453,8 +588,6 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
             count);
     }
     SQ_LAUNCHED("lsh_emit_small_kernel");
-    rc = scan_exclusive_u64(bpoff, big_cap, reinterpret_cast<const uint64_t *>(counters + 2), rscratch, st);
-    if (rc != SUBQUAD_OK) return rc;
     {
         const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
         ProfScope prof("lsh_emit_kernel", st);
