@@ -382,12 +382,14 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
 // pair, no gathers): with ubar = dL/du and z = W1 x + b1 recomputed from x,
 //   dW1[k] += ubar w2_k [z_k > 0] x,  db1[k] += ubar w2_k [z_k > 0],
 //   dw2[k] += ubar relu(z_k),          db2 += ubar.
-// Lane l of a 16-lane group owns units l + 16 m; float64 accumulators, reduced per block and
-// added into wacc (dW1[H][4], db1[H], dw2[H], db2).
+// Lane l of a 16-lane group owns units l + 16 m; float64 accumulators, reduced per block
+// into column-major partials wpart[col][block] over the 6H + 1 values (dW1[H][4], db1[H],
+// dw2[H], db2), which gate_ws_reduce_kernel sums in a fixed order (no atomics: the weight
+// gradients are reproducible bit for bit).
 template <int UNITS>
 __global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, const float4 *__restrict__ pack,
                                                                   const float4 *__restrict__ feat,
-                                                                  double *__restrict__ wacc) {
+                                                                  double *__restrict__ wpart) {
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
@@ -457,31 +459,45 @@ __global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, con
         double sacc = 0.0;
 #pragma unroll
         for (int ww = 0; ww < kGateThreads / 64; ++ww) sacc += red[ww][ll][m];
+        int col;
         if (m == kVals) {
-            if (ll == 0) atomicAdd(&wacc[in.H * 6], sacc);
-            continue;
+            if (ll != 0) continue;  // every lane group holds the same db2 sum
+            col = in.H * 6;
+        } else {
+            const int k = m / 6, qq = m - k * 6;
+            const int unit = ll + kGroup * k;
+            col = qq < 4 ? unit * 4 + qq : (qq == 4 ? in.H * 4 + unit : in.H * 5 + unit);
         }
-        const int k = m / 6, qq = m - k * 6;
-        const int unit = ll + kGroup * k;
-        double *dst;
-        if (qq < 4) dst = &wacc[unit * 4 + qq];
-        else if (qq == 4) dst = &wacc[in.H * 4 + unit];
-        else dst = &wacc[in.H * 5 + unit];
-        atomicAdd(dst, sacc);
+        wpart[(int64_t)col * gridDim.x + blockIdx.x] = sacc;
     }
 }
 
-__global__ void gate_ws_zero_kernel(double *__restrict__ wacc, int count) {
-    for (int k = threadIdx.x; k < count; k += blockDim.x) wacc[k] = 0.0;
-}
+constexpr int kReduceThreads = 256;
 
-__global__ void gate_ws_finish_kernel(const double *__restrict__ wacc, int H, float *__restrict__ dW1,
-                                      float *__restrict__ db1, float *__restrict__ dw2, float *__restrict__ db2) {
-    for (int k = threadIdx.x; k < H * 6 + 1; k += blockDim.x) {
-        float v = (float)wacc[k];
-        if (k < H * 4) dW1[k] += v;
-        else if (k < H * 5) db1[k - H * 4] += v;
-        else if (k < H * 6) dw2[k - H * 5] += v;
+// Column col of the weight-gradient partials summed over the nblocks blocks in a fixed
+// order, rounded to float32 and added to its output.
+__global__ __launch_bounds__(kReduceThreads) void gate_ws_reduce_kernel(const double *__restrict__ wpart,
+                                                                        int64_t nblocks, int H,
+                                                                        float *__restrict__ dW1,
+                                                                        float *__restrict__ db1,
+                                                                        float *__restrict__ dw2,
+                                                                        float *__restrict__ db2) {
+    __shared__ double red[kReduceThreads];
+    const int col = blockIdx.x;
+    const double *row = wpart + (int64_t)col * nblocks;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += kReduceThreads) acc += row[b];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int half = kReduceThreads / 2; half > 0; half >>= 1) {
+        if (threadIdx.x < half) red[threadIdx.x] += red[threadIdx.x + half];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float v = (float)red[0];
+        if (col < H * 4) dW1[col] += v;
+        else if (col < H * 5) db1[col - H * 4] += v;
+        else if (col < H * 6) dw2[col - H * 5] += v;
         else db2[0] += v;
     }
 }
@@ -531,7 +547,8 @@ struct GateOrders {
 
 template <int NV, bool TRAIN>
 static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, int64_t *lblocks, const GateOrders &o,
-                       float4 *pack, float4 *feat, float *demb, double *wacc, hipStream_t st) {
+                       float4 *pack, float4 *feat, float *demb, double *wpart, float *dW1, float *db1, float *dw2,
+                       float *db2, hipStream_t st) {
     const uint64_t *order_j = o.order_j;
     switch (in.H / kGroup) {
 #define SQ_CASE(U)                                                                                                 \
@@ -547,9 +564,12 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
         {                                                                                                          \
             const int64_t blocks = gate_blocks(in.P, (const void *)gate_wgrad_kernel<U>);                          \
             ProfScope prof("gate_wgrad_kernel", st);                                                               \
-            gate_wgrad_kernel<U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, pack, feat, wacc);                 \
+            gate_wgrad_kernel<U><<<(unsigned)blocks, kGateThreads, 0, st>>>(in, pack, feat, wpart);                \
+            SQ_LAUNCHED("gate_wgrad_kernel");                                                                      \
+            gate_ws_reduce_kernel<<<(unsigned)(in.H * 6 + 1), kReduceThreads, 0, st>>>(wpart, blocks, in.H, dW1,     \
+                                                                                       db1, dw2, db2);             \
         }                                                                                                          \
-        SQ_LAUNCHED("gate_wgrad_kernel");                                                                          \
+        SQ_LAUNCHED("gate_ws_reduce_kernel");                                                                      \
         break;                                                                                                     \
     }
         SQ_CASE(1) SQ_CASE(2) SQ_CASE(4) SQ_CASE(8) SQ_CASE(16)
@@ -572,14 +592,14 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
 static int64_t gate_max_blocks() { return (int64_t)device_cus() * 8; }
 
 struct GateBwdLayout {
-    size_t wacc, ra, rb, rc, rd, pack, feat, node, lpart, flags, radix, total;
+    size_t wpart, ra, rb, rc, rd, pack, feat, node, lpart, flags, radix, total;
 };
 
 static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
     GateBwdLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
-    L.wacc = take(sizeof(double) * (size_t)(H * 6 + 1));
+    L.wpart = take(sizeof(double) * (size_t)(H * 6 + 1) * (size_t)gate_max_blocks());
     L.ra = take(sizeof(uint64_t) * P);
     L.rb = take(sizeof(uint64_t) * P);
     L.rc = take(sizeof(uint64_t) * P);
@@ -765,9 +785,7 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
         }
         return SUBQUAD_OK;
     }
-    double *wacc = reinterpret_cast<double *>(w + L.wacc);
-    gate_ws_zero_kernel<<<1, 256, 0, st>>>(wacc, in.H * 6 + 1);
-    SQ_LAUNCHED("gate_ws_zero_kernel");
+    double *wpart = reinterpret_cast<double *>(w + L.wpart);
     int4 *node = reinterpret_cast<int4 *>(w + L.node);
     if (in.n > 0) {
         gate_node_pack_kernel<<<(unsigned)std::min<int64_t>(ceil_div(in.n, 256), (int64_t)device_cus() * 16), 256, 0,
@@ -783,14 +801,17 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
     const TrainOut tr{margin, 1.f / (float)in.P, fused, lpart};
     int64_t lblocks = 0;
     const int nv = (int)ceil_div(in.d / 4, kGroup);
-    if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
-    else if (nv <= 2) rc = gate_bwd_nv<2, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
-    else if (nv <= 4) rc = gate_bwd_nv<4, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
-    else if (nv <= 8) rc = gate_bwd_nv<8, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
-    else rc = gate_bwd_nv<16, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wacc, st);
+    if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
+                                               db2, st);
+    else if (nv <= 2) rc = gate_bwd_nv<2, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
+                                               db2, st);
+    else if (nv <= 4) rc = gate_bwd_nv<4, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
+                                               db2, st);
+    else if (nv <= 8) rc = gate_bwd_nv<8, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
+                                               db2, st);
+    else rc = gate_bwd_nv<16, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
+                                               db2, st);
     if (rc != SUBQUAD_OK) return rc;
-    gate_ws_finish_kernel<<<1, 256, 0, st>>>(wacc, in.H, dW1, db1, dw2, db2);
-    SQ_LAUNCHED("gate_ws_finish_kernel");
     if (TRAIN) {
         contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, (int)lblocks, in.P, loss);
         SQ_LAUNCHED("contrastive_final_kernel");

@@ -329,41 +329,76 @@ __device__ __forceinline__ unsigned long long block_slot(unsigned long long *cou
 
 constexpr int kEmitThreads = 256;
 
-// Step 3b, short runs (<= kSmallRun records): a block takes 256 runs, scans their pair
-// counts in LDS, and its threads walk the block's pairs in rounds of 256 (a pair finds its
-// run by bisection in LDS; k-th pair of a run: y = the largest y with y(y-1)/2 <= k,
-// x = k - y(y-1)/2).
+constexpr int kEmitPer = 4;                           // runs per thread of a chunk
+constexpr int kEmitRuns = kEmitThreads * kEmitPer;    // runs per chunk
+constexpr int kEmitBuf = 1024;                        // kept keys buffered per block
+
+// Step 3b, short runs (<= kSmallRun records): a block takes chunks of kEmitRuns runs, scans
+// their pair counts in LDS, and its threads walk the chunk's pairs in rounds of 256 (a pair
+// finds its run by bisection in LDS; k-th pair of a run: y = the largest y with
+// y(y-1)/2 <= k, x = k - y(y-1)/2).  Kept keys collect in LDS and leave in batches, one
+// global atomic per batch.
 __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
     const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
     const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
     const uint64_t *__restrict__ runs, const unsigned long long *__restrict__ counters, uint64_t *__restrict__ pkeys,
     int64_t cap, unsigned long long *__restrict__ count) {
-    __shared__ uint32_t vend[kEmitThreads];  // inclusive prefix of the runs' pair counts
-    __shared__ uint64_t rsh[kEmitThreads];
-    __shared__ uint32_t lcount;
+    __shared__ uint32_t vend[kEmitRuns];  // inclusive prefix of the runs' pair counts
+    __shared__ uint32_t rsh[kEmitRuns];  // first record of each run
+    __shared__ uint64_t kbuf[kEmitBuf];
+    __shared__ uint32_t wt[kEmitThreads / 64];
+    __shared__ uint32_t kn;
     __shared__ unsigned long long gbase;
     const int64_t nruns = (int64_t)counters[0];
     const uint32_t n32 = (uint32_t)n;
-    for (int64_t tile = (int64_t)blockIdx.x * kEmitThreads; tile < nruns; tile += (int64_t)gridDim.x * kEmitThreads) {
-        const int64_t t = tile + threadIdx.x;
-        const uint64_t run = t < nruns ? runs[t] : 0ull;
-        const uint32_t m = (uint32_t)run;  // 0 for a slot whose run is long
-        rsh[threadIdx.x] = run;
-        vend[threadIdx.x] = m * (m - (m > 0)) / 2;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) kn = 0u;
+    // moves the buffered keys out (all threads call it)
+    auto flush = [&]() {
         __syncthreads();
-        for (int off = 1; off < kEmitThreads; off <<= 1) {
-            const uint32_t v = threadIdx.x >= off ? vend[threadIdx.x - off] : 0u;
-            __syncthreads();
-            vend[threadIdx.x] += v;
-            __syncthreads();
+        const uint32_t cnt = kn;
+        if (t == 0 && cnt) gbase = atomicAdd(count, (unsigned long long)cnt);
+        __syncthreads();
+        for (uint32_t x = t; x < cnt; x += kEmitThreads)
+            if ((int64_t)(gbase + x) < cap) pkeys[gbase + x] = kbuf[x];
+        __syncthreads();
+        if (t == 0) kn = 0u;
+        __syncthreads();
+    };
+    for (int64_t tile = (int64_t)blockIdx.x * kEmitRuns; tile < nruns; tile += (int64_t)gridDim.x * kEmitRuns) {
+        // thread t takes runs 4t .. 4t+3 of the chunk
+        uint32_t c[kEmitPer], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kEmitPer; ++k) {
+            const int64_t q = tile + t * kEmitPer + k;
+            const uint64_t run = q < nruns ? runs[q] : 0ull;
+            const uint32_t m = (uint32_t)run;  // 0 for a slot whose run is long
+            rsh[t * kEmitPer + k] = (uint32_t)(run >> 32);
+            c[k] = m * (m - (m > 0)) / 2;
+            sum += c[k];
         }
-        const uint32_t V = vend[kEmitThreads - 1];
+        // block inclusive scan of the thread sums: wave scan, then the wave totals
+        uint32_t inc = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) wt[w] = inc;
+        __syncthreads();
+        for (int ww = 0; ww < w; ++ww) inc += wt[ww];
+        uint32_t run_end = inc - sum;
+#pragma unroll
+        for (int k = 0; k < kEmitPer; ++k) {
+            run_end += c[k];
+            vend[t * kEmitPer + k] = run_end;
+        }
+        __syncthreads();
+        const uint32_t V = vend[kEmitRuns - 1];
         for (uint32_t v0 = 0; v0 < V; v0 += kEmitThreads) {
-            const uint32_t v = v0 + threadIdx.x;
-            bool want = false;
-            int64_t i = 0, j = 0;
+            const uint32_t v = v0 + t;
             if (v < V) {
-                int lo = 0, hi = kEmitThreads - 1;  // first run with vend > v
+                int lo = 0, hi = kEmitRuns - 1;  // first run with vend > v
                 while (lo < hi) {
                     const int mid = (lo + hi) >> 1;
                     if (vend[mid] > v) hi = mid; else lo = mid + 1;
@@ -372,15 +407,18 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
                 uint32_t y = 1;
                 while ((y + 1) * y / 2 <= k) ++y;  // y < kSmallRun
                 const uint32_t x = k - y * (y - 1) / 2;
-                const int64_t start = (int64_t)(rsh[lo] >> 32);
-                want = pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs,
-                                       R, i, j);
+                const int64_t start = (int64_t)rsh[lo];
+                int64_t i = 0, j = 0;
+                if (pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs,
+                                    R, i, j))
+                    kbuf[atomicAdd(&kn, 1u)] = ((uint64_t)i << nb) | (uint64_t)j;
             }
-            const unsigned long long slot = block_slot(count, want, &lcount, &gbase);
-            if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+            __syncthreads();
+            if (kn > kEmitBuf - kEmitThreads) flush();  // room for one more round
         }
-        __syncthreads();  // vend and rsh are reused by the next tile
+        __syncthreads();  // vend, rsh and wt are reused by the next chunk
     }
+    flush();
 }
 
 // Step 3b, long runs: one thread per (run, x < y) pair of records, the long runs' pairs
