@@ -11,9 +11,22 @@ constexpr int kGroup = 16;
 // them: more gathers in flight per group.
 constexpr int kGateBatch = 4;
 
+// v moved across the lanes of each 16-lane row by the DPP control `ctrl`.
+template <int ctrl>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+}
+
+// Sum over the 16 lanes of a group (a DPP row), in every lane, with no LDS traffic: swap
+// within pairs (quad_perm 1,0,3,2), within quads (quad_perm 2,3,0,1), across the quads of
+// each half row (row_half_mirror), across the half rows (row_mirror).  Each step adds two
+// equal partial sums in either order, so all 16 lanes end with the same bits.
 __device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-    for (int off = kGroup / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kGroup);
+    static_assert(kGroup == 16, "group_sum works on DPP rows of 16 lanes");
+    v += dpp_f32<0xB1>(v);
+    v += dpp_f32<0x4E>(v);
+    v += dpp_f32<0x141>(v);
+    v += dpp_f32<0x140>(v);
     return v;
 }
 
