@@ -275,15 +275,29 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     int4 ni = make_int4(0, 0, 0, 0);
     int64_t cur_i = -1;
     bool started_here = false;
+    // The pair indices of the next batch are fetched while the current one is computed:
+    // pn = pair number, inx = i (-1: no pair), jnx = j.
+    uint32_t pn[kGateBatch];
+    int32_t inx[kGateBatch], jnx[kGateBatch];
+    auto fetch = [&](int64_t qb) {
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) {
+            const int64_t qq = qb + u;
+            const bool live = qq < q1;
+            const uint32_t pp = live ? (natural ? (uint32_t)qq : (uint32_t)order_i[qq]) : 0u;
+            pn[u] = pp;
+            inx[u] = live ? in.pairs[2 * (int64_t)pp] : -1;
+            jnx[u] = live ? in.pairs[2 * (int64_t)pp + 1] : -1;
+        }
+    };
+    fetch(q0);
     for (int64_t q = q0; q < q1; q += kGateBatch) {
         int64_t pb[kGateBatch], ib[kGateBatch], jb[kGateBatch];
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u)
-            pb[u] = q + u < q1 ? (natural ? q + u : (int64_t)(uint32_t)order_i[q + u]) : -1;
-#pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
-            ib[u] = pb[u] >= 0 ? in.pairs[2 * pb[u]] : -1;
-            jb[u] = pb[u] >= 0 ? in.pairs[2 * pb[u] + 1] : -1;
+            pb[u] = q + u < q1 ? (int64_t)pn[u] : -1;
+            ib[u] = inx[u];
+            jb[u] = jnx[u];
         }
         PairLoad<NV> pl[kGateBatch];
         float gfb[kGateBatch];
@@ -292,6 +306,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             load_pair<NV>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
             if (!TRAIN) gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
         }
+        if (q + kGateBatch < q1) fetch(q + kGateBatch);
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
             if (pb[u] < 0) break;

@@ -125,12 +125,19 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     float inv_nu2 = 0.f;
     int64_t cur = -1;
     bool started_here = false;
+    // the next batch's order records are fetched while the current one is computed
+    uint64_t nrec[kGateBatch];
+#pragma unroll
+    for (int t = 0; t < kGateBatch; ++t) nrec[t] = q0 + t < q1 ? order_j[q0 + t] : ~0ull;
     for (int64_t qb = q0; qb < q1; qb += kGateBatch) {
         int64_t ub[kGateBatch], ib[kGateBatch];
         float4 pk[kGateBatch];
+        uint64_t recs[kGateBatch];
+#pragma unroll
+        for (int t = 0; t < kGateBatch; ++t) recs[t] = nrec[t];
 #pragma unroll
         for (int t = 0; t < kGateBatch; ++t) {
-            const uint64_t rec = qb + t < q1 ? order_j[qb + t] : ~0ull;
+            const uint64_t rec = recs[t];
             ub[t] = qb + t < q1 ? (int64_t)(rec >> 32) : -1;
             const int64_t p = (int64_t)(uint32_t)rec;
             const bool live = ub[t] >= 0 && ub[t] < n && p < P;
@@ -143,6 +150,11 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
             const bool use = pk[t].x != 0.f && ib[t] >= 0 && ib[t] < n;
             if (!use) ib[t] = -1;
             if (use) load_row<NV>(emb, ib[t], d4, l, ep[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kGateBatch; ++t) {
+            const int64_t qn = qb + kGateBatch + t;
+            nrec[t] = qn < q1 ? order_j[qn] : ~0ull;
         }
 #pragma unroll
         for (int t = 0; t < kGateBatch; ++t) {
