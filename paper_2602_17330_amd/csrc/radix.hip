@@ -15,6 +15,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;
 
+// idx, or the last valid index when idx is past the end (count >= 1): lets a loop issue all
+// of its loads unconditionally, masking the values afterwards.
+__device__ __forceinline__ int64_t clamp_index(int64_t idx, int64_t count) { return idx < count ? idx : count - 1; }
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -39,11 +43,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
                                                                    int64_t count, uint32_t *__restrict__ partial) {
     __shared__ uint32_t wt[4];
     int64_t base = (int64_t)blockIdx.x * kScanChunk;
-    uint32_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (idx < count) s += data[idx];
-    }
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = data[clamp_index(base + (int64_t)k * kScanThreads + threadIdx.x, count)];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + (int64_t)k * kScanThreads + threadIdx.x < count) s += v[k];
     uint32_t inc = block_inclusive_scan(s, wt);
     if (threadIdx.x == kScanThreads - 1) partial[blockIdx.x] = inc;
 }
@@ -74,9 +79,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__re
     uint32_t v[kScanItems];
     uint32_t s = 0;
 #pragma unroll
+    for (int k = 0; k < kScanItems; ++k) v[k] = data[clamp_index(base + k, count)];
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + k;
-        v[k] = idx < count ? data[idx] : 0;
+        if (base + k >= count) v[k] = 0;
         s += v[k];
     }
     uint32_t inc = block_inclusive_scan(s, wt);
@@ -135,9 +141,14 @@ __global__ __launch_bounds__(kScanThreads) void scan64_reduce_kernel(const uint6
     const int64_t count = count_of(cap, count_dev);
     int64_t base = (int64_t)blockIdx.x * kScanChunk;
     uint64_t s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
-        if (idx < count) s += data[idx];
+    if (base < count) {  // count may be below the launch's capacity
+        uint64_t v[kScanItems];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            v[k] = data[clamp_index(base + (int64_t)k * kScanThreads + threadIdx.x, count)];
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + (int64_t)k * kScanThreads + threadIdx.x < count) s += v[k];
     }
     uint64_t inc = block_inclusive_scan64(s, wt);
     if (threadIdx.x == kScanThreads - 1) partial[blockIdx.x] = inc;
@@ -168,10 +179,13 @@ __global__ __launch_bounds__(kScanThreads) void scan64_apply_kernel(uint64_t *__
     int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     uint64_t v[kScanItems];
     uint64_t s = 0;
+    if (count > 0) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = data[clamp_index(base + k, count)];
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + k;
-        v[k] = idx < count ? data[idx] : 0;
+        if (base + k >= count) v[k] = 0;
         s += v[k];
     }
     uint64_t inc = block_inclusive_scan64(s, wt);
@@ -217,10 +231,18 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     if (base < n) {
-#pragma unroll 4
+        // all loads in flight before any is used (an index past the end reads the last record
+        // and is not counted)
+        uint64_t v[kRadixItems];
+#pragma unroll
         for (int k = 0; k < kRadixItems; ++k) {
-            int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
-            if (idx < n) atomicAdd(&h[(uint32_t)(in[idx] >> shift) & dmask], 1u);
+            const int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
+            v[k] = in[idx < n ? idx : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kRadixItems; ++k) {
+            const int64_t idx = base + (int64_t)k * kRadixThreads + threadIdx.x;
+            if (idx < n) atomicAdd(&h[(uint32_t)(v[k] >> shift) & dmask], 1u);
         }
     }
     __syncthreads();
@@ -248,11 +270,18 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
     const uint64_t lt = lanemask_lt(lane);
     uint64_t rec[kRadixItems];
     uint32_t rank[kRadixItems];
+    // the tile's loads all issue before the ranking starts (an index past the end reads the
+    // last record; it is not ranked or written)
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        const int64_t idx = base + (int64_t)k * 64 + lane;
+        rec[k] = in[idx < n ? idx : n - 1];
+    }
+    const uint32_t my_base = hist[(int64_t)t * nblocks + blockIdx.x];  // kRadixThreads == kRadixBuckets
 #pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
         int64_t idx = base + (int64_t)k * 64 + lane;
         bool valid = idx < n;
-        rec[k] = valid ? in[idx] : 0ull;
         uint32_t d = (uint32_t)(rec[k] >> shift) & dmask;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
             wc[ww][d] = tot;
             tot += c;
         }
-        gbase[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+        gbase[d] = my_base;
     }
     uint32_t inc = block_inclusive_scan(tot, wt);
     tile_off[t] = inc - tot;
