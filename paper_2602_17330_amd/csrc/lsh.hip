@@ -37,6 +37,8 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 
 // Step 1. Block = 64 sequences x b bands.  Reads of the signature rows are contiguous
 // (item e = s * b + beta), record stores are contiguous per band (staged through LDS).
+// R4: r == 4 with 16-byte aligned tuples, each read as two 16-byte loads.
+template <bool R4>
 __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     const uint64_t *__restrict__ sig, int64_t n, int32_t M, int32_t b, int32_t r,
     const int64_t *__restrict__ offs, int64_t R, uint32_t keep, uint32_t band_in_key, uint64_t *__restrict__ rec,
@@ -59,12 +61,29 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
             const uint64_t rep = ok && R > 1 ? (uint64_t)rep_of(offs, R, i) : 0ull;
             h[u] = mix64(rep * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull + (uint64_t)beta);
         }
-        for (int k = 0; k < r; ++k) {
-            uint64_t w[kKeysUnroll];
+        if (R4) {
+            ulonglong2 w[kKeysUnroll][2];
 #pragma unroll
-            for (int u = 0; u < kKeysUnroll; ++u) w[u] = tup[u] ? tup[u][k] : 0ull;
+            for (int u = 0; u < kKeysUnroll; ++u) {
+                const ulonglong2 *t2 = reinterpret_cast<const ulonglong2 *>(tup[u] ? tup[u] : sig);
+                w[u][0] = t2[0];
+                w[u][1] = t2[1];
+            }
 #pragma unroll
-            for (int u = 0; u < kKeysUnroll; ++u) h[u] = mix64(h[u] ^ w[u]);
+            for (int u = 0; u < kKeysUnroll; ++u) {
+                h[u] = mix64(h[u] ^ w[u][0].x);
+                h[u] = mix64(h[u] ^ w[u][0].y);
+                h[u] = mix64(h[u] ^ w[u][1].x);
+                h[u] = mix64(h[u] ^ w[u][1].y);
+            }
+        } else {
+            for (int k = 0; k < r; ++k) {
+                uint64_t w[kKeysUnroll];
+#pragma unroll
+                for (int u = 0; u < kKeysUnroll; ++u) w[u] = tup[u] ? tup[u][k] : 0ull;
+#pragma unroll
+                for (int u = 0; u < kKeysUnroll; ++u) h[u] = mix64(h[u] ^ w[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < kKeysUnroll; ++u) {
@@ -313,6 +332,36 @@ __device__ __forceinline__ bool pair_found_here(uint32_t la, uint32_t lb, uint32
     return !earlier_band(sig, M, F, b, r, i, j, beta);
 }
 
+// pair_found_here for 32 bands of 4 words with 16-byte aligned signature rows: the two
+// tuples and the two fingerprint rows are loaded together (16-byte loads), before any test.
+__device__ __forceinline__ bool pair_found_here_b32r4(uint32_t la, uint32_t lb, uint32_t n32,
+                                                      const uint64_t *__restrict__ sig, int32_t M,
+                                                      const uint8_t *__restrict__ F, const int64_t *__restrict__ offs,
+                                                      int64_t R, int64_t &i, int64_t &j) {
+    const int beta = (int)(la / n32);
+    if (beta >= 32) return false;
+    i = (int64_t)(la - (uint32_t)beta * n32);
+    j = (int64_t)(lb - (uint32_t)beta * n32);
+    const ulonglong2 *ti = reinterpret_cast<const ulonglong2 *>(sig + i * M + beta * 4);
+    const ulonglong2 *tj = reinterpret_cast<const ulonglong2 *>(sig + j * M + beta * 4);
+    const uint4 *fi = reinterpret_cast<const uint4 *>(F + i * 32);
+    const uint4 *fj = reinterpret_cast<const uint4 *>(F + j * 32);
+    const ulonglong2 a0 = ti[0], a1 = ti[1], c0 = tj[0], c1 = tj[1];
+    const uint4 fi0 = fi[0], fi1 = fi[1], fj0 = fj[0], fj1 = fj[1];
+    if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) return false;
+    if (a0.x != c0.x || a0.y != c0.y || a1.x != c1.x || a1.y != c1.y) return false;
+    const uint32_t x[8] = {fi0.x ^ fj0.x, fi0.y ^ fj0.y, fi0.z ^ fj0.z, fi0.w ^ fj0.w,
+                           fi1.x ^ fj1.x, fi1.y ^ fj1.y, fi1.z ^ fj1.z, fi1.w ^ fj1.w};
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+        if (4 * w >= beta) break;
+        for (int k = 0; k < 4 && 4 * w + k < beta; ++k)
+            if (((x[w] >> (8 * k)) & 0xFFu) == 0u && tuple_equal(sig, M, i, j, 4 * w + k, 4))
+                return false;  // equal tuples in an earlier band: the pair is emitted there
+    }
+    return true;
+}
+
 // Slots in the pair-key list for the threads of a block that want one: an LDS counter
 // hands out block-local ranks, then one global atomic per block reserves them.  Every
 // thread of the block must call it (it synchronises the block).
@@ -338,6 +387,7 @@ constexpr int kEmitBuf = 1024;                        // kept keys buffered per 
 // finds its run by bisection in LDS; k-th pair of a run: y = the largest y with
 // y(y-1)/2 <= k, x = k - y(y-1)/2).  Kept keys collect in LDS and leave in batches, one
 // global atomic per batch.
+template <bool B32R4>
 __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
     const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
     const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
@@ -409,8 +459,9 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
                 const uint32_t x = k - y * (y - 1) / 2;
                 const int64_t start = (int64_t)rsh[lo];
                 int64_t i = 0, j = 0;
-                if (pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs,
-                                    R, i, j))
+                const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
+                if (B32R4 ? pair_found_here_b32r4(la, lb, n32, sig, M, F, offs, R, i, j)
+                          : pair_found_here(la, lb, n32, sig, M, b, r, F, offs, R, i, j))
                     kbuf[atomicAdd(&kn, 1u)] = ((uint64_t)i << nb) | (uint64_t)j;
             }
             __syncthreads();
@@ -578,8 +629,11 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     SQ_REQUIRE(lds <= 64 * 1024, SUBQUAD_ERR_ARG, "too many bands");
     {
         ProfScope prof("lsh_keys_kernel", st);
-        lsh_keys_kernel<<<(unsigned)ceil_div(n, kKeysTileSeqs), kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R,
-                                                                                          keep, band_in_key, rec_a, F);
+        const unsigned g = (unsigned)ceil_div(n, kKeysTileSeqs);
+        if (r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0)
+            lsh_keys_kernel<true><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, F);
+        else
+            lsh_keys_kernel<false><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, F);
     }
     SQ_LAUNCHED("lsh_keys_kernel");
     uint64_t *sorted = nullptr;
@@ -621,9 +675,14 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     }
     {
         ProfScope prof("lsh_emit_small_kernel", st);
-        lsh_emit_small_kernel<<<(unsigned)((int64_t)device_cus() * 8), kEmitThreads, 0, st>>>(
-            sorted, n, sig, M, b, r, F, offs, R, nb, runs, counters, reinterpret_cast<uint64_t *>(ws + L.pk_a), cap,
-            count);
+        const unsigned g = (unsigned)((int64_t)device_cus() * 8);
+        uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
+        if (b == 32 && r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0)
+            lsh_emit_small_kernel<true><<<g, kEmitThreads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, runs,
+                                                                    counters, pk, cap, count);
+        else
+            lsh_emit_small_kernel<false><<<g, kEmitThreads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, runs,
+                                                                     counters, pk, cap, count);
     }
     SQ_LAUNCHED("lsh_emit_small_kernel");
     {
