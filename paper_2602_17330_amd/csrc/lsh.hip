@@ -475,6 +475,7 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
 // Step 3b, long runs: one thread per (run, x < y) pair of records, the long runs' pairs
 // flattened by the prefix sum of their pair counts; k-th pair of a run: y = the largest y
 // with y(y-1)/2 <= k, x = k - y(y-1)/2.
+template <bool B32R4>
 __global__ __launch_bounds__(1024) void lsh_emit_kernel(
     const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
     const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
@@ -503,8 +504,9 @@ __global__ __launch_bounds__(1024) void lsh_emit_kernel(
             while (y * (y - 1) / 2 > k) --y;
             while ((y + 1) * y / 2 <= k) ++y;
             const uint64_t x = k - y * (y - 1) / 2;
-            want = pair_found_here((uint32_t)srec[start + x], (uint32_t)srec[start + y], n32, sig, M, b, r, F, offs, R,
-                                   i, j);
+            const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
+            want = B32R4 ? pair_found_here_b32r4(la, lb, n32, sig, M, F, offs, R, i, j)
+                         : pair_found_here(la, lb, n32, sig, M, b, r, F, offs, R, i, j);
         }
         const unsigned long long slot = block_slot(count, want, &lcount, &gbase);
         if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
@@ -673,11 +675,13 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
         }
         SQ_LAUNCHED("lsh_compact_kernel");
     }
+    // 32 bands of 4 words, 16-byte aligned rows: the pair test with fused loads
+    const bool b32r4 = b == 32 && r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0;
     {
         ProfScope prof("lsh_emit_small_kernel", st);
         const unsigned g = (unsigned)((int64_t)device_cus() * 8);
         uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
-        if (b == 32 && r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0)
+        if (b32r4)
             lsh_emit_small_kernel<true><<<g, kEmitThreads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, runs,
                                                                     counters, pk, cap, count);
         else
@@ -688,9 +692,14 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     {
         const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
         ProfScope prof("lsh_emit_kernel", st);
-        lsh_emit_kernel<<<(unsigned)((int64_t)device_cus() * 16), emit_threads, 0, st>>>(
-            sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff, counters,
-            reinterpret_cast<uint64_t *>(ws + L.pk_a), cap, count);
+        const unsigned g = (unsigned)((int64_t)device_cus() * 16);
+        uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
+        if (b32r4)
+            lsh_emit_kernel<true><<<g, emit_threads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff,
+                                                              counters, pk, cap, count);
+        else
+            lsh_emit_kernel<false><<<g, emit_threads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff,
+                                                               counters, pk, cap, count);
     }
     SQ_LAUNCHED("lsh_emit_kernel");
     return SUBQUAD_OK;
