@@ -103,7 +103,7 @@ struct PairFeat {
 template <int NV>
 __device__ __forceinline__ PairFeat pair_features(const PairLoad<NV> &pl, int4 ni) {
     PairFeat f;
-    f.s = (float)pl.al / sqrtf((float)ni.x * (float)pl.nj.x);
+    f.s = (float)pl.al * rsqrt_fast((float)ni.x * (float)pl.nj.x);
     f.x2 = fabsf((float)(ni.y - pl.nj.y));
     f.x3 = ni.z == pl.nj.z ? 1.f : 0.f;
     f.same_label = ni.w == pl.nj.w;
@@ -120,7 +120,7 @@ __device__ __forceinline__ float unit_preact(const float (&w)[4], float b, float
 // except z, the lane's own hidden units).
 template <int UNITS>
 struct PairState {
-    float c, ni, nj, g, gm, u;
+    float c, ni, nj, inv, g, gm, u;  // inv = 1 / (|e_i| |e_j|), 0 for a zero row
     bool ok;
     float z[UNITS];
 };
@@ -137,11 +137,12 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
     }
     dot = group_sum(dot);
     nj2 = group_sum(nj2);
-    st.ni = sqrtf(ni2);
-    st.nj = sqrtf(nj2);
+    st.ni = sqrt_fast(ni2);
+    st.nj = sqrt_fast(nj2);
     const float den = st.ni * st.nj;
     st.ok = den >= 1e-12f;
-    st.c = st.ok ? dot / den : 0.f;
+    st.inv = st.ok ? rcp_fast(den) : 0.f;
+    st.c = dot * st.inv;
     float part = 0.f;
 #pragma unroll
     for (int k = 0; k < UNITS; ++k) {
@@ -152,8 +153,12 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
         part += r[5] * fmaxf(st.z[k], 0.f);
     }
     st.u = group_sum(part) + b2;
-    st.g = 1.f / (1.f + expf(-st.u));
-    st.gm = 1.f / (1.f + expf(st.u));  // 1 - g without cancellation
+    // g = sigmoid(u) and gm = 1 - g from one exponential of -|u| (no overflow, and gm
+    // without the cancellation of 1 - g)
+    const float t = exp2_fast(-fabsf(st.u) * 1.44269504f);
+    const float r = rcp_fast(1.f + t);
+    st.g = st.u >= 0.f ? r : t * r;
+    st.gm = st.u >= 0.f ? t * r : r;
 }
 
 template <int UNITS>
@@ -360,13 +365,13 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
                 xc += st.z[k] > 0.f ? r[1] * r[5] : 0.f;
             }
             const float cbar = gf * st.gm + ubar * group_sum(xc);
-            const float inv = st.ok ? 1.f / (st.ni * st.nj) : 0.f;
+            const float inv = st.inv;
             if (l == 0) {
                 pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
                 feat[p] = make_float4(ft.s, st.c, ft.x2, ft.x3);
             }
             if (demb && st.ok) {
-                const float ci = st.c / (st.ni * st.ni);
+                const float ci = st.c * rcp_fast(st.ni * st.ni);
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
                     gi[k].x += cbar * (pl[u].ej[k].x * inv - ci * ei[k].x);

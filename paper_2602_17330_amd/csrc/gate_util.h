@@ -11,6 +11,14 @@ constexpr int kGroup = 16;
 // them: more gathers in flight per group.
 constexpr int kGateBatch = 4;
 
+// Hardware reciprocal, square root, reciprocal square root and 2^x (about 1 ulp each; the
+// gate's tolerance against the float64 reference is 1e-5 relative).  Every gate kernel uses
+// the same ones, so the forward and the backward take the same ReLU decisions.
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
 // v moved across the lanes of each 16-lane row by the DPP control `ctrl`.
 template <int ctrl>
 __device__ __forceinline__ float dpp_f32(float v) {
