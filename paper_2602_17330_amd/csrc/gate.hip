@@ -150,7 +150,7 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
         const float4 w = *reinterpret_cast<const float4 *>(r);
         const float wv[4] = {w.x, w.y, w.z, w.w};
         st.z[k] = unit_preact(wv, r[4], ft.s, st.c, ft.x2, ft.x3);
-        part += r[5] * fmaxf(st.z[k], 0.f);
+        part = fmaf(r[5], fmaxf(st.z[k], 0.f), part);
     }
     st.u = group_sum(part) + b2;
     // g = sigmoid(u) and gm = 1 - g from one exponential of -|u| (no overflow, and gm
@@ -159,6 +159,12 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
     const float r = rcp_fast(1.f + t);
     st.g = st.u >= 0.f ? r : t * r;
     st.gm = st.u >= 0.f ? t * r : r;
+}
+
+// f = g s + (1 - g) c as one fixed fma (the forward and the training pass agree bit for bit).
+template <int UNITS>
+__device__ __forceinline__ float fused_value(const PairState<UNITS> &st, const PairFeat &ft) {
+    return fmaf(st.g, ft.s, st.gm * st.c);
 }
 
 template <int UNITS>
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
             PairState<UNITS> st;
             pair_forward<NV, UNITS>(ei, ni2, pl[u], ft, wsh, l, b2, st);
             if (l == 0) {
-                fused[p + u] = st.g * ft.s + st.gm * st.c;
+                fused[p + u] = fused_value(st, ft);
                 if (gate) gate[p + u] = st.g;
             }
         }
@@ -253,26 +259,16 @@ struct TrainOut {
 // recomputes the forward, accumulates e_i's gradient in registers over its row, and stores
 // per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
 // feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
-template <int NV, int UNITS, bool TRAIN>
-__global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const float *__restrict__ gfused,
-                                                                const uint64_t *__restrict__ order_nat,
-                                                                const uint64_t *__restrict__ order_sorted,
-                                                                const int64_t *__restrict__ unsorted,
-                                                                float4 *__restrict__ pack, float4 *__restrict__ feat,
-                                                                float *__restrict__ demb, TrainOut tr) {
-    // Pairs already in order of i (the candidate lists are): walk them as they are, p = q.
-    const bool natural = unsorted[0] == 0;
-    const uint64_t *__restrict__ order_i = natural ? order_nat : order_sorted;
-    const int l = threadIdx.x & (kGroup - 1);
-    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
-    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(in.P, ngroups);
-    const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
+// The walk of gate_bwd_kernel over the chunk [q0, q1) of one lane group (NATURAL: the pairs
+// are in order of i, p = q); returns the group's sum of loss terms (TRAIN, lane 0).
+template <int NV, int UNITS, bool TRAIN, bool NATURAL>
+__device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *__restrict__ gfused,
+                                                const uint64_t *__restrict__ order_i, const float *wsh,
+                                                float4 *__restrict__ pack, float4 *__restrict__ feat,
+                                                float *__restrict__ demb, const TrainOut &tr, int64_t q0,
+                                                int64_t q1, int l, int d4, float b2) {
     double loss_acc = 0.0;
-    const int d4 = in.d >> 2;
-    __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
-    stage_weights(in, wsh);
-    const float b2 = in.b2[0];
+    if (q0 >= q1) return loss_acc;
     float4 ei[NV], gi[NV], old[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -281,18 +277,19 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
     int64_t cur_i = -1;
     bool started_here = false;
     // The pair indices of the next batch are fetched while the current one is computed:
-    // pn = pair number, inx = i (-1: no pair), jnx = j.
+    // pn = pair number, inx = i, jnx = j.  The loads are unconditional (indices past the
+    // chunk are clamped to its last pair, and such entries are dropped at use), so that no
+    // wait follows them.
     uint32_t pn[kGateBatch];
     int32_t inx[kGateBatch], jnx[kGateBatch];
     auto fetch = [&](int64_t qb) {
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
-            const int64_t qq = qb + u;
-            const bool live = qq < q1;
-            const uint32_t pp = live ? (natural ? (uint32_t)qq : (uint32_t)order_i[qq]) : 0u;
+            const int64_t qq = min(qb + u, q1 - 1);
+            const uint32_t pp = NATURAL ? (uint32_t)qq : (uint32_t)order_i[qq];
             pn[u] = pp;
-            inx[u] = live ? in.pairs[2 * (int64_t)pp] : -1;
-            jnx[u] = live ? in.pairs[2 * (int64_t)pp + 1] : -1;
+            inx[u] = in.pairs[2 * (int64_t)pp];
+            jnx[u] = in.pairs[2 * (int64_t)pp + 1];
         }
     };
     fetch(q0);
@@ -300,9 +297,10 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
         int64_t pb[kGateBatch], ib[kGateBatch], jb[kGateBatch];
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
-            pb[u] = q + u < q1 ? (int64_t)pn[u] : -1;
-            ib[u] = inx[u];
-            jb[u] = jnx[u];
+            const bool live = q + u < q1;
+            pb[u] = live ? (int64_t)pn[u] : -1;
+            ib[u] = live ? inx[u] : -1;
+            jb[u] = live ? jnx[u] : -1;
         }
         PairLoad<NV> pl[kGateBatch];
         float gfb[kGateBatch];
@@ -339,7 +337,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
             pair_forward<NV, UNITS>(ei, ni2, pl[u], ft, wsh, l, b2, st);
             float gf;
             if (TRAIN) {
-                const float f = st.g * ft.s + st.gm * st.c;
+                const float f = fused_value(st, ft);
                 float lp;
                 if (ft.same_label) {
                     const float e = 1.f - f;
@@ -386,6 +384,32 @@ __global__ __launch_bounds__(kGateThreads) void gate_bwd_kernel(GateIn in, const
         const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
         flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here && ends_here);
     }
+    return loss_acc;
+}
+
+// (Three waves per SIMD: the register budget is capped at 168 so that the TRAIN variant
+// keeps that occupancy.)
+template <int NV, int UNITS, bool TRAIN>
+__global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void gate_bwd_kernel(
+    GateIn in, const float *__restrict__ gfused, const uint64_t *__restrict__ order_nat,
+    const uint64_t *__restrict__ order_sorted, const int64_t *__restrict__ unsorted, float4 *__restrict__ pack,
+    float4 *__restrict__ feat, float *__restrict__ demb, TrainOut tr) {
+    // Pairs already in order of i (the candidate lists are): walk them as they are, p = q.
+    const bool natural = unsorted[0] == 0;
+    const uint64_t *__restrict__ order_i = natural ? order_nat : order_sorted;
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = ceil_div(in.P, ngroups);
+    const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
+    const int d4 = in.d >> 2;
+    __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
+    stage_weights(in, wsh);
+    const float b2 = in.b2[0];
+    const double loss_acc = natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat,
+                                                                            demb, tr, q0, q1, l, d4, b2)
+                                    : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat,
+                                                                             demb, tr, q0, q1, l, d4, b2);
     if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
         __shared__ double red[kGateThreads];
         red[threadIdx.x] = loss_acc;

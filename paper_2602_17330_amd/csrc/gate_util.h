@@ -48,7 +48,11 @@ __device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t 
     }
 }
 
-__device__ __forceinline__ float dot4(float4 a, float4 b) { return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w; }
+// One fixed fma chain (with contraction left to the compiler, two kernels could round the
+// same dot product differently).
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+    return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
+}
 
 // Adds a row's accumulated gradient slice into demb.  A row whose pairs all lie inside one
 // group's chunk is owned by that group (plain read-modify-write); a row split across
