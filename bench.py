@@ -462,6 +462,10 @@ def main():
 
     n = rep.n
     M, b, r, d = cfg.M, cfg.b, cfg.r, emb.shape[1]
+    pr = pipe.pairs[:P].long()
+    rows_i = int(torch.unique(pr[:, 0]).numel())  # distinct first indices
+    rows_j = int(torch.unique(pr[:, 1]).numel())
+    del pr
     recs = n * b
     # algorithmic bytes (or int32 ops) of ONE launch of each kernel
     alg = {
@@ -474,11 +478,13 @@ def main():
         "lsh_emit_small_kernel": ("hbm", recs * 8 + 8 * P),
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),
-        # the fused gate pass: forward, loss and backward, 2*d*4 + 16 (rows and scalars) + 4 (the
-        # fused value) + 2*d*4 (dE) bytes per pair, split over its two passes: rows by i write
-        # e_i's gradient, rows by j write e_j's
-        "gate_bwd_kernel": ("hbm", P * (2 * d * 4 + 20 + d * 4)),
-        "gate_cos_bwd_j_kernel": ("hbm", P * d * 4),
+        # the fused gate pass, compulsory bytes: per pair its partner row, records and outputs,
+        # per distinct row its own row, gradient row in and gradient row out (rows by i in the
+        # first pass, rows by j in the second)
+        "gate_bwd_kernel": ("hbm", P * (4 * d + 16 + 4 + 8) + rows_i * (4 * d + 4 * d + 16)
+                            + P * (16 + 16 + 4) + rows_i * 4 * d),
+        "gate_cos_bwd_j_kernel": ("hbm", P * (8 + 16 + 4 + 4 * d) + rows_j * (4 * d + 4 * d)
+                                  + rows_j * 4 * d),
         # (the i-order sort has no roofline entry: the candidate pairs arrive in order of i,
         # so its device-side record count is zero and its launches return at once)
         "sort_gate_j_scatter": ("hbm", 2 * P * 8),
