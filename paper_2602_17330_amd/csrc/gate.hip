@@ -266,7 +266,8 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                                                 const uint64_t *__restrict__ order_i, const float *wsh,
                                                 float4 *__restrict__ pack, float4 *__restrict__ feat,
                                                 float *__restrict__ demb, const TrainOut &tr, int64_t q0,
-                                                int64_t q1, int l, int d4, float b2) {
+                                                int64_t q1, int l, int d4, float b2, float4 (*stage)[2],
+                                                float *fstage) {
     double loss_acc = 0.0;
     if (q0 >= q1) return loss_acc;
     float4 ei[NV], gi[NV], old[NV];
@@ -316,9 +317,9 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
             const int64_t p = pb[u];
             if (pl[u].i < 0) {  // out-of-range pair: skipped
                 if (l == 0) {
-                    pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    feat[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (TRAIN && tr.fused) tr.fused[p] = __builtin_nanf("");
+                    stage[u][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    stage[u][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    fstage[u] = __builtin_nanf("");
                 }
                 continue;
             }
@@ -350,7 +351,7 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                 }
                 if (l == 0) {
                     loss_acc += (double)lp;
-                    if (tr.fused) tr.fused[p] = f;
+                    fstage[u] = f;
                 }
             } else {
                 gf = gfb[u];
@@ -365,8 +366,8 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
             const float cbar = gf * st.gm + ubar * group_sum(xc);
             const float inv = st.inv;
             if (l == 0) {
-                pack[p] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
-                feat[p] = make_float4(ft.s, st.c, ft.x2, ft.x3);
+                stage[u][0] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
+                stage[u][1] = make_float4(ft.s, st.c, ft.x2, ft.x3);
             }
             if (demb && st.ok) {
                 const float ci = st.c * rcp_fast(st.ni * st.ni);
@@ -378,6 +379,16 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                     gi[k].w += cbar * (pl[u].ej[k].w * inv - ci * ei[k].w);
                 }
             }
+        }
+        // the batch's per-pair records leave together: lane u stores pair u's (consecutive
+        // pairs give one contiguous store per array)
+        int64_t mine = -1;  // the pair this lane stores (lane u: pair u)
+#pragma unroll
+        for (int u = 0; u < kGateBatch; ++u) mine = l == u ? pb[u] : mine;
+        if (mine >= 0) {
+            pack[mine] = stage[l][0];
+            feat[mine] = stage[l][1];
+            if (TRAIN && tr.fused) tr.fused[mine] = fstage[l];
         }
     }
     if (cur_i >= 0 && demb) {
@@ -406,10 +417,15 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
     stage_weights(in, wsh);
     const float b2 = in.b2[0];
-    const double loss_acc = natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat,
-                                                                            demb, tr, q0, q1, l, d4, b2)
-                                    : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat,
-                                                                             demb, tr, q0, q1, l, d4, b2);
+    // per lane group: the current batch's pack and feat records and fused values
+    __shared__ float4 stage[kGateThreads / kGroup][kGateBatch][2];
+    __shared__ float fstage[kGateThreads / kGroup][kGateBatch];
+    const int g = threadIdx.x / kGroup;
+    const double loss_acc =
+        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat, demb, tr, q0, q1, l, d4,
+                                                        b2, stage[g], fstage[g])
+                : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat, demb, tr, q0, q1, l,
+                                                         d4, b2, stage[g], fstage[g]);
     if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
         __shared__ double red[kGateThreads];
         red[threadIdx.x] = loss_acc;
