@@ -111,8 +111,8 @@ size_t subquad_lsh_workspace_bytes(int64_t n, int32_t b, int64_t cap);
 /*
  * subquad_lsh_candidates -- candidate list CAND of the MinHash LSH index (Algorithm 1,
  * preprocessing; index of Sec. 4.2; cost O(|C|) + O(n log n), Appendix B).
- *   sig [n][M] u64: signatures from subquad_minhash.  b bands of r rows, b * r <= M; band
- *   beta covers signature rows beta*r .. beta*r + r - 1.
+ *   sig [n][M] u64: signatures from subquad_minhash.  b bands of r rows, 1 <= b <= 256,
+ *   b * r <= M; band beta covers signature rows beta*r .. beta*r + r - 1.
  *   rep_offsets [R+1] i64 (may be NULL, then R must be 1): repertoire r is rows
  *   rep_offsets[r] .. rep_offsets[r+1]-1; rep_offsets[0] = 0, rep_offsets[R] = n, ascending.
  *   ws / ws_bytes: workspace of at least subquad_lsh_workspace_bytes(n, b, cap) bytes,

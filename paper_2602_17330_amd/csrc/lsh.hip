@@ -592,8 +592,8 @@ static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
 static int lsh_validate(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32_t r, const int64_t *offs,
                         int64_t R, void *ws, size_t ws_bytes, int32_t *pairs, int64_t cap) {
     SQ_REQUIRE(n >= 0 && cap >= 0, SUBQUAD_ERR_ARG, "n and cap must be >= 0");
-    SQ_REQUIRE(b >= 1 && r >= 1 && (int64_t)b * r <= M && M <= 4096, SUBQUAD_ERR_ARG,
-               "need b >= 1, r >= 1, b*r <= M (b=%d r=%d M=%d)", b, r, M);
+    SQ_REQUIRE(b >= 1 && b <= 256 && r >= 1 && (int64_t)b * r <= M && M <= 4096, SUBQUAD_ERR_ARG,
+               "need 1 <= b <= 256, r >= 1, b*r <= M (b=%d r=%d M=%d)", b, r, M);
     SQ_REQUIRE(n * (int64_t)b < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "n*b must be below 2^32");
     SQ_REQUIRE(n < (int64_t(1) << 31), SUBQUAD_ERR_ARG, "n must be below 2^31");
     SQ_REQUIRE(R >= 1 && (R == 1 || offs), SUBQUAD_ERR_ARG, "R >= 1 and rep_offsets required when R > 1");
@@ -624,11 +624,10 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     // radix digits, so a small repertoire sorts in fewer passes.
     const int mix_bits = record_mix_bits(n);
     const uint32_t keep = mix_bits >= 32 ? ~0u : ~((1u << (32 - mix_bits)) - 1u);
-    // the band goes into the cleared bits when they can hold it: runs then compare whole
-    // key words, with no division by n
-    const uint32_t band_in_key = mix_bits <= 24 && b <= 256 ? 1u : 0u;
-    const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;
-    SQ_REQUIRE(lds <= 64 * 1024, SUBQUAD_ERR_ARG, "too many bands");
+    // the band (b <= 256) goes into the cleared bits when there are any: runs then compare
+    // whole key words, with no division by n
+    const uint32_t band_in_key = mix_bits <= 24 ? 1u : 0u;
+    const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;  // at most 64 KiB (b <= 256)
     {
         ProfScope prof("lsh_keys_kernel", st);
         const unsigned g = (unsigned)ceil_div(n, kKeysTileSeqs);

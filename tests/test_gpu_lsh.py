@@ -44,6 +44,29 @@ def test_band_shapes(b, r, M):
     assert _rows_ok(got, rows, rep.n)
 
 
+def test_band_count_limit():
+    """b > 256 is refused before any launch (the band must fit the key's spare bits and the
+    key kernel's LDS)."""
+    sig = np.zeros((10, 300), np.uint64)
+    with pytest.raises(sq.SubquadError, match="b <= 256"):
+        _gpu(sig, 257, 1)
+
+
+def test_over_2p20_rows_full_key():
+    """n = 2^20 + 12,345 rows: the record sort keeps all 32 mix bits (four passes) and the
+    band is compared by division.  Random words from 2^22 values per band, so about 2^17
+    chance collisions per band, checked against the oracle."""
+    n = (1 << 20) + 12345
+    rng = np.random.default_rng(2)
+    sig = rng.integers(0, 1 << 22, size=(n, 2), dtype=np.uint64)
+    say(f"lsh n={n} 2x1 random words")
+    got, rows = _gpu(sig, 2, 1, cap=1 << 20)
+    ref = olsh.candidates(sig, 2, 1)
+    assert ref.shape[0] > 100_000
+    assert np.array_equal(got, ref)
+    assert _rows_ok(got, rows, n)
+
+
 def test_large_identical_bucket():
     """600 copies of one signature: one bucket holding every pair (skewed run)."""
     rep = synth.tiny(n_families=20, fam_size=5, seed=31)
