@@ -25,7 +25,7 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t q) {
     return z ^ (z >> 31);
 }
 
-constexpr int kMinhashBlock = 512;
+constexpr int kMinhashBlock = 1024;
 constexpr uint32_t kPosMask = 63u;  // shingle positions 0..61 (stride <= 64)
 
 // Median of three unsigned words (one VALU instruction).
