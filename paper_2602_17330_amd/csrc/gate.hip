@@ -69,7 +69,7 @@ __device__ __forceinline__ void stage_weights(const GateIn &in, float *wsh) {
 // out-of-range pair loads node 0 and row 0), so a batch's loads are all in flight together.
 template <int NV>
 struct PairLoad {
-    int32_t p, i, j;  // i < 0: no pair (past the chunk, or out of range); p < 2^32 is validated
+    int32_t i;  // i < 0: no pair (past the chunk, or out of range)
     int4 nj;          // (self score, length, V-gene, label) of j (label 0 without packed records)
     int32_t al;
     float4 ej[NV];
@@ -83,10 +83,8 @@ __device__ __forceinline__ int4 node_record(const GateIn &in, int64_t k) {
 template <int NV>
 __device__ __forceinline__ void load_pair(const GateIn &in, int64_t p, int64_t i, int64_t j, int d4, int l,
                                           PairLoad<NV> &pl) {
-    pl.p = (int32_t)p;
     const bool ok = p >= 0 && i >= 0 && j >= 0 && i < in.n && j < in.n;
     pl.i = ok ? (int32_t)i : -1;
-    pl.j = ok ? (int32_t)j : -1;
     if (in.n == 0) return;  // no row to stand in (every pair is out of range)
     const int64_t js = ok ? j : 0, ps = ok ? p : 0;
     pl.nj = node_record(in, js);
