@@ -32,7 +32,8 @@ struct RmtScalars {  // device-resident Lanczos state
     int32_t pad;
 };
 
-// y = A_tau x: entries with 0 < v < tau (compared in float64).
+// y = A_tau x: entries with 0 < v < tau (compared in float64).  16 lanes per row (four per
+// row measured slower: rows of the similarity graph vary widely in length).
 __global__ __launch_bounds__(kRmtThreads) void rmt_spmv_kernel(const int64_t *__restrict__ ro,
                                                                const int32_t *__restrict__ cols,
                                                                const float *__restrict__ vals, int64_t n, double tau,
@@ -63,9 +64,19 @@ __global__ __launch_bounds__(kRmtThreads) void rmt_mdot_kernel(const float *__re
     double acc = 0.0;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int64_t base = c * kRmtChunk;
+        // the chunk's loads all issue before the products (indices past n are clamped and
+        // their terms skipped; the sum runs in the same order as a plain loop)
+        float vv[kRmtChunk / kRmtThreads], ww[kRmtChunk / kRmtThreads];
+#pragma unroll
+        for (int u = 0; u < kRmtChunk / kRmtThreads; ++u) {
+            const int64_t i = min(base + u * kRmtThreads + threadIdx.x, n - 1);
+            vv[u] = v[i];
+            ww[u] = w[i];
+        }
         double part = 0.0;
-        for (int64_t i = base + threadIdx.x; i < min(n, base + kRmtChunk); i += kRmtThreads)
-            part += (double)v[i] * (double)w[i];
+#pragma unroll
+        for (int u = 0; u < kRmtChunk / kRmtThreads; ++u)
+            if (base + u * kRmtThreads + threadIdx.x < n) part += (double)vv[u] * (double)ww[u];
         acc += part;
     }
     __shared__ double red[kRmtThreads];
@@ -108,7 +119,16 @@ __global__ __launch_bounds__(kRmtThreads) void rmt_msub_kernel(const float *__re
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kRmtThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRmtThreads) {
         double s = (double)w[i];
-        for (int j = 0; j <= k; ++j) s -= h[j] * (double)V[(int64_t)j * n + i];
+        // eight basis entries in flight at a time (same subtraction order as one by one)
+        int j = 0;
+        for (; j + 8 <= k + 1; j += 8) {
+            float vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vv[u] = V[(int64_t)(j + u) * n + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s -= h[j + u] * (double)vv[u];
+        }
+        for (; j <= k; ++j) s -= h[j] * (double)V[(int64_t)j * n + i];
         const float f = (float)s;
         w[i] = f;
         acc += (double)f * (double)f;
@@ -211,19 +231,20 @@ __global__ void rmt_start_done_kernel(RmtScalars *__restrict__ sc) {
     if (threadIdx.x == 0 && blockIdx.x == 0) sc->beta[0] = 0.0;
 }
 
-// Largest eigenvalue of T (diagonal alpha[0..m), off-diagonal beta[1..m)) by bisection on
-// the Sturm count (number of eigenvalues below x from the LDL^T pivots).
-__global__ void rmt_tridiag_kernel(RmtScalars *__restrict__ sc) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int m = sc->steps;
+// Largest eigenvalue of T_m (diagonal alpha[0..m), off-diagonal beta[1..m)): multisection
+// on the Sturm count (the number of eigenvalues below x, from the LDL^T pivots) by the 64
+// lanes of one wave, each testing one of 64 interior points, from the Gershgorin interval
+// down to a width of 1e-15 relative; returns the interval's upper end (every lane the same).
+__device__ double ritz_max(const RmtScalars *__restrict__ sc, int m) {
+    const int t = threadIdx.x & 63;
     double lo = 0.0, hi = 0.0;
     for (int i = 0; i < m; ++i) {
         const double r = (i > 0 ? fabs(sc->beta[i]) : 0.0) + (i + 1 < m ? fabs(sc->beta[i + 1]) : 0.0);
         lo = i == 0 ? sc->alpha[i] - r : fmin(lo, sc->alpha[i] - r);
         hi = i == 0 ? sc->alpha[i] + r : fmax(hi, sc->alpha[i] + r);
     }
-    for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
-        const double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 64 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+        const double x = lo + (hi - lo) * (double)(t + 1) / 65.0;
         int below = 0;
         double q = 1.0;
         for (int i = 0; i < m; ++i) {
@@ -232,10 +253,32 @@ __global__ void rmt_tridiag_kernel(RmtScalars *__restrict__ sc) {
             if (q == 0.0) q = -1e-300;
             below += q < 0.0;
         }
-        if (below == m) hi = x;  // every eigenvalue is below x
-        else lo = x;
+        // the first point above every eigenvalue bounds the largest one from above; the
+        // point before it (or lo) bounds it from below
+        const uint64_t above = __ballot(below == m);
+        const int f = above ? __builtin_ctzll(above) : 64;
+        const double nlo = lo + (hi - lo) * (double)f / 65.0;
+        const double nhi = f == 64 ? hi : lo + (hi - lo) * (double)(f + 1) / 65.0;
+        lo = nlo;
+        hi = nhi;
     }
-    sc->lambda = hi;
+    return hi;
+}
+
+// lambda = largest eigenvalue of T over the steps taken (one wave).
+__global__ __launch_bounds__(64) void rmt_tridiag_kernel(RmtScalars *__restrict__ sc) {
+    const double lam = ritz_max(sc, sc->steps);
+    if (threadIdx.x == 0) sc->lambda = lam;
+}
+
+// After step k: when the largest Ritz value of T_{k+1} already exceeds `target`, the run
+// stops there (later steps return at once).  Ritz values of Lanczos only grow with the
+// step count, so the run's answer to "is lambda_max above target?" is the one all steps
+// would give.  One wave.
+__global__ __launch_bounds__(64) void rmt_check_kernel(RmtScalars *__restrict__ sc, int k, double target) {
+    if (sc->steps <= k) return;
+    const double theta = ritz_max(sc, k + 1);
+    if (threadIdx.x == 0 && theta > target) sc->steps = k + 1;
 }
 
 // sumsq and max of the values (two-stage: block partials, then one block).
@@ -315,8 +358,13 @@ static RmtLayout rmt_layout(int64_t n, int32_t K) {
 }
 
 // lambda_max(A_tau) by K Lanczos steps; leaves it in sc->lambda (device).
+constexpr int kRmtCheckEvery = 8;  // steps between early-stop checks
+
+// stop_above: finite for a threshold decision (stop once a Ritz value exceeds it), INFINITY
+// for the eigenvalue itself.
 static int rmt_lanczos(const int64_t *ro, const int32_t *cols, const float *vals, int64_t n, double tau, int K,
-                       uint64_t seed, char *ws, const RmtLayout &L, hipStream_t st) {
+                       uint64_t seed, char *ws, const RmtLayout &L, hipStream_t st,
+                       double stop_above = INFINITY) {
     float *V = reinterpret_cast<float *>(ws + L.V);
     float *w = reinterpret_cast<float *>(ws + L.w);
     double *h = reinterpret_cast<double *>(ws + L.h);
@@ -355,6 +403,10 @@ static int rmt_lanczos(const int64_t *ro, const int32_t *cols, const float *vals
         SQ_LAUNCHED("rmt_norm_kernel");
         rmt_scale_kernel<<<(unsigned)vb, kRmtThreads, 0, st>>>(w, V + (int64_t)(k + 1) * n, n, sc, k);
         SQ_LAUNCHED("rmt_scale_kernel");
+        if (std::isfinite(stop_above) && (k + 1) % kRmtCheckEvery == 0 && k + 1 < K) {
+            rmt_check_kernel<<<1, 64, 0, st>>>(sc, k, stop_above);
+            SQ_LAUNCHED("rmt_check_kernel");
+        }
     }
     rmt_tridiag_kernel<<<1, 64, 0, st>>>(sc);
     SQ_LAUNCHED("rmt_tridiag_kernel");
@@ -417,7 +469,7 @@ extern "C" int subquad_rmt_threshold(const int64_t *row_offsets, const int32_t *
     double lo = 0.0, hi = wmax;
     for (int it = 0; it < iters; ++it) {
         const double mid = 0.5 * (lo + hi);
-        rc = rmt_lanczos(row_offsets, cols, vals, n, mid, steps, seed, w, L, st);
+        rc = rmt_lanczos(row_offsets, cols, vals, n, mid, steps, seed, w, L, st, lp);
         if (rc != SUBQUAD_OK) return rc;
         double lam = 0.0;
         SQ_HIP(hipMemcpyAsync(&lam, &sc->lambda, sizeof(double), hipMemcpyDeviceToHost, st));
