@@ -97,19 +97,35 @@ static AlignLayout align_layout(int64_t P) {
     return L;
 }
 
+// Table offsets of the row pairs (x, x+1) of the shorter sequence: its first ROWS bytes are
+// read as words, all loads issued together (word indices clamped to the row's last word,
+// aw_max; bytes at x >= la are masked), instead of one dependent byte load per row.
+template <int ROWS>
+__device__ __forceinline__ void row_pair_codes(const uint8_t *__restrict__ arow, int la, int aw_max,
+                                               uint32_t (&idx2)[ROWS / 2]) {
+    constexpr int NW = (ROWS + 3) / 4;
+    const uint32_t *aw = reinterpret_cast<const uint32_t *>(arow);
+    uint32_t w[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = aw[min(k, aw_max)];
+#pragma unroll
+    for (int k = 0; k < ROWS / 2; ++k) {
+        const int x0 = 2 * k, x1 = 2 * k + 1;
+        const int b0 = (int)((w[x0 >> 2] >> (8 * (x0 & 3))) & 0xFFu);
+        const int b1 = (int)((w[x1 >> 2] >> (8 * (x1 & 3))) & 0xFFu);
+        const int c0 = x0 < la ? min(b0, 19) : kMaskCode;
+        const int c1 = x1 < la ? min(b1, 19) : kMaskCode;
+        idx2[k] = (uint32_t)(c0 * kCodes + c1);
+    }
+}
+
 // DP of one pair in one lane.  a: the shorter sequence (rows), b: the longer (columns).
 template <int ROWS>
 __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la, const uint8_t *__restrict__ brow,
-                                       int lb, const uint32_t *__restrict__ S2, int go, int ge) {
+                                       int lb, const uint32_t *__restrict__ S2, int go, int ge, int aw_max) {
     // byte offsets into S2 of the row pair (x, x+1), without the column-residue part
     uint32_t idx2[ROWS / 2];
-#pragma unroll
-    for (int k = 0; k < ROWS / 2; ++k) {
-        int x0 = 2 * k, x1 = 2 * k + 1;
-        int c0 = x0 < la ? min((int)arow[x0], 19) : kMaskCode;
-        int c1 = x1 < la ? min((int)arow[x1], 19) : kMaskCode;
-        idx2[k] = (uint32_t)(c0 * kCodes + c1);
-    }
+    row_pair_codes<ROWS>(arow, la, aw_max, idx2);
     int Hp[ROWS], E[ROWS], HG[ROWS];
 #pragma unroll
     for (int x = 0; x < ROWS; ++x) {
@@ -164,15 +180,9 @@ __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la,
 // answer D[la][lb] is picked out of the register column by an unrolled select.
 template <int ROWS>
 __device__ __forceinline__ int ed_lane(const uint8_t *__restrict__ arow, int la, const uint8_t *__restrict__ brow,
-                                       int lb, const uint32_t *__restrict__ C2, int indel) {
+                                       int lb, const uint32_t *__restrict__ C2, int indel, int aw_max) {
     uint32_t idx2[ROWS / 2];
-#pragma unroll
-    for (int k = 0; k < ROWS / 2; ++k) {
-        int x0 = 2 * k, x1 = 2 * k + 1;
-        int c0 = x0 < la ? min((int)arow[x0], 19) : kMaskCode;
-        int c1 = x1 < la ? min((int)arow[x1], 19) : kMaskCode;
-        idx2[k] = (uint32_t)(c0 * kCodes + c1);
-    }
+    row_pair_codes<ROWS>(arow, la, aw_max, idx2);
     int D[ROWS];  // D[x] holds row x + 1 of the current column
 #pragma unroll
     for (int x = 0; x < ROWS; ++x) D[x] = (x + 1) * indel;  // column 0
@@ -233,17 +243,20 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
     if (lo >= hi) return;  // whole grid
     if ((int64_t)blockIdx.x * (kAlignThreads / 64) >= ceil_div(hi - lo, 64)) return;  // whole block
     __shared__ uint32_t S2[kS2Words];
+    __shared__ int8_t sub_sh[20 * 20];  // the 400 scores, loaded once (one load per thread)
+    for (int e = threadIdx.x; e < 20 * 20; e += blockDim.x) sub_sh[e] = subst[e];
+    __syncthreads();
     for (int e = threadIdx.x; e < kS2Words; e += blockDim.x) {
         int c = e / (kCodes * kCodes);
         int rem = e - c * (kCodes * kCodes);
         int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
         int s0, s1;
         if (MODE == 0) {
-            s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : kMaskScore;
-            s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : kMaskScore;
+            s0 = a0 < 20 ? (int)sub_sh[a0 * 20 + c] : kMaskScore;
+            s1 = a1 < 20 ? (int)sub_sh[a1 * 20 + c] : kMaskScore;
         } else {  // costs; rows past the end are never read back
-            s0 = a0 < 20 ? (int)subst[a0 * 20 + c] : 0;
-            s1 = a1 < 20 ? (int)subst[a1 * 20 + c] : 0;
+            s0 = a0 < 20 ? (int)sub_sh[a0 * 20 + c] : 0;
+            s1 = a1 < 20 ? (int)sub_sh[a1 * 20 + c] : 0;
         }
         S2[e] = ((uint32_t)(uint16_t)(int16_t)s0) | ((uint32_t)(uint16_t)(int16_t)s1 << 16);
     }
@@ -271,8 +284,8 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
             int la, lb;
             if (li <= lj) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
             else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
-            if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge);
-            else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go);
+            if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge, (stride >> 2) - 1);
+            else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, (stride >> 2) - 1);
         }
     }
 }
