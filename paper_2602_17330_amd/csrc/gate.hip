@@ -80,16 +80,21 @@ __device__ __forceinline__ int4 node_record(const GateIn &in, int64_t k) {
     return in.node ? in.node[k] : make_int4(in.self[k], in.lens[k], in.vgene[k], 0);
 }
 
-template <int NV>
+// PACKED: in.node is set (the backward packs the records first), and the loads go out with
+// no branch between them.
+template <int NV, bool PACKED = false>
 __device__ __forceinline__ void load_pair(const GateIn &in, int64_t p, int64_t i, int64_t j, int d4, int l,
                                           PairLoad<NV> &pl) {
     const bool ok = p >= 0 && i >= 0 && j >= 0 && i < in.n && j < in.n;
     pl.i = ok ? (int32_t)i : -1;
-    if (in.n == 0) return;  // no row to stand in (every pair is out of range)
+    // no row to stand in when there are none (every pair is out of range; a PACKED caller
+    // handles that case before it loads anything)
+    if (!PACKED && in.n == 0) return;
     const int64_t js = ok ? j : 0, ps = ok ? p : 0;
-    pl.nj = node_record(in, js);
+    pl.nj = PACKED ? in.node[js] : node_record(in, js);
     pl.al = in.align[ps];
-    load_row<NV>(in.emb, js, d4, l, pl.ej);
+    if (PACKED) load_row_flat<NV>(in.emb, js, d4, l, pl.ej);
+    else load_row<NV>(in.emb, js, d4, l, pl.ej);
 }
 
 // The pair's integer features: s = A / sqrt(S_i S_j), |L_i - L_j|, [V_i = V_j], same label.
@@ -268,6 +273,15 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                                                 float *fstage) {
     double loss_acc = 0.0;
     if (q0 >= q1) return loss_acc;
+    if (in.n == 0) {  // no rows: every pair is out of range
+        for (int64_t q = q0 + l; q < q1; q += kGroup) {
+            const int64_t p = NATURAL ? q : (int64_t)(uint32_t)order_i[q];
+            pack[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            feat[p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (TRAIN && tr.fused) tr.fused[p] = __builtin_nanf("");
+        }
+        return loss_acc;
+    }
     float4 ei[NV], gi[NV], old[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -305,7 +319,7 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
         float gfb[kGateBatch];
 #pragma unroll
         for (int u = 0; u < kGateBatch; ++u) {
-            load_pair<NV>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
+            load_pair<NV, true>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
             if (!TRAIN) gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
         }
         if (q + kGateBatch < q1) fetch(q + kGateBatch);
@@ -328,7 +342,7 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
                 if (demb) load_grad_row<NV>(demb, i, d4, l, old);
-                ni = node_record(in, i);
+                ni = in.node[i];
                 load_row_norm<NV>(in, i, d4, l, ei, ni2);
             }
             const PairFeat ft = pair_features<NV>(pl[u], ni);

@@ -48,6 +48,23 @@ __device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t 
     }
 }
 
+// load_row with no branch around the loads: slots past the row are clamped into it and
+// zeroed after the load, so that a batch's row loads can all be in flight together.
+template <int NV>
+__device__ __forceinline__ void load_row_flat(const float *__restrict__ emb, int64_t row, int d4, int l,
+                                              float4 (&v)[NV]) {
+    const float4 *r = reinterpret_cast<const float4 *>(emb) + row * d4;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const int c = l + kGroup * k;
+        const float4 x = r[min(c, d4 - 1)];
+        // a bit mask rather than a select, so the compiler cannot move the load under a branch
+        const int m = c < d4 ? -1 : 0;
+        v[k] = make_float4(__int_as_float(__float_as_int(x.x) & m), __int_as_float(__float_as_int(x.y) & m),
+                           __int_as_float(__float_as_int(x.z) & m), __int_as_float(__float_as_int(x.w) & m));
+    }
+}
+
 // One fixed fma chain (with contraction left to the compiler, two kernels could round the
 // same dot product differently).
 __device__ __forceinline__ float dot4(float4 a, float4 b) {
