@@ -166,12 +166,19 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
         for (int t = 0; t < kGateBatch; ++t) recs[t] = nrec[t];
 #pragma unroll
         for (int t = 0; t < kGateBatch; ++t) {
+            // loads with no branch around them (a dead entry reads pair 0; its values are
+            // masked out), so that the batch's loads are in flight together
             const uint64_t rec = recs[t];
             ub[t] = qb + t < q1 ? (int64_t)(rec >> 32) : -1;
-            const int64_t p = (int64_t)(uint32_t)rec;
-            const bool live = ub[t] >= 0 && ub[t] < n && p < P;
-            pk[t] = live ? pack[p] : make_float4(0.f, 0.f, 0.f, 0.f);
-            ib[t] = live ? pairs[2 * p] : -1;
+            const int64_t pr = (int64_t)(uint32_t)rec;
+            const bool live = ub[t] >= 0 && ub[t] < n && pr < P;
+            const int64_t p = live ? pr : 0;
+            const float4 pv = pack[p];
+            const int32_t iv = pairs[2 * p];
+            const int m = live ? -1 : 0;
+            pk[t] = make_float4(__int_as_float(__float_as_int(pv.x) & m), __int_as_float(__float_as_int(pv.y) & m),
+                                __int_as_float(__float_as_int(pv.z) & m), __int_as_float(__float_as_int(pv.w) & m));
+            ib[t] = live ? iv : -1;
         }
         float4 ep[kGateBatch][NV];
 #pragma unroll
