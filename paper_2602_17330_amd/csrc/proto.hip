@@ -81,11 +81,25 @@ __device__ __forceinline__ void load_fixed(const float *__restrict__ src, int64_
 template <int D, class RowOf>
 __device__ __forceinline__ void stage_tile(float *tile, const float *__restrict__ src, RowOf rowof) {
     constexpr int LD = D + 4, Q = D / 4;
-    for (int e = threadIdx.x; e < 32 * Q; e += kProtoThreads) {
-        const int i = e / Q, q = e - i * Q;
+    constexpr int kPer = (32 * Q + kProtoThreads - 1) / kProtoThreads;  // float4 per thread
+    // every load of the tile is issued before the first store: an absent row reads row 0
+    // and is zeroed with a bit mask (a select would let the compiler put the load behind a
+    // branch, with a wait after each)
+    float4 v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kProtoThreads;
+        const int i = min(e / Q, 31), q = e - (e / Q) * Q;
         const int64_t row = rowof(i);
-        const float4 v = row >= 0 ? reinterpret_cast<const float4 *>(src + row * D)[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        *reinterpret_cast<float4 *>(tile + i * LD + 4 * q) = v;
+        v[u] = reinterpret_cast<const float4 *>(src + (row >= 0 ? row : 0) * D)[q];
+        const int m = (row >= 0 && e < 32 * Q) ? -1 : 0;
+        v[u] = make_float4(__int_as_float(__float_as_int(v[u].x) & m), __int_as_float(__float_as_int(v[u].y) & m),
+                           __int_as_float(__float_as_int(v[u].z) & m), __int_as_float(__float_as_int(v[u].w) & m));
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int e = threadIdx.x + u * kProtoThreads;
+        if (e < 32 * Q) *reinterpret_cast<float4 *>(tile + (e / Q) * LD + 4 * (e % Q)) = v[u];
     }
 }
 
@@ -592,7 +606,7 @@ static int proto_bwd_d(const ProtoIn &in, char *w, const ProtoLayout &L, const f
                                                                                                  grad_loss, tps, demb);
     }
     SQ_LAUNCHED("proto_bwd_rows_kernel");
-    if (!through) return SUBQUAD_OK;
+    if (!through || in.n == 0) return SUBQUAD_OK;  // (no rows: nothing routes back; tiles stage emb rows)
     float *dP = reinterpret_cast<float *>(w + L.dP);
     {
         const int64_t bx = ceil_div(in.C, kProtoRows);
