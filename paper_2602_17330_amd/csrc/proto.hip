@@ -78,16 +78,17 @@ __device__ __forceinline__ void load_fixed(const float *__restrict__ src, int64_
 }
 
 // Stages 32 rows (src row of tile entry i = rowof(i), -1 for zeros) into LDS.
-template <int D, class RowOf>
-__device__ __forceinline__ void stage_tile(float *tile, const float *__restrict__ src, RowOf rowof) {
-    constexpr int LD = D + 4, Q = D / 4;
-    constexpr int kPer = (32 * Q + kProtoThreads - 1) / kProtoThreads;  // float4 per thread
-    // every load of the tile is issued before the first store: an absent row reads row 0
-    // and is zeroed with a bit mask (a select would let the compiler put the load behind a
-    // branch, with a wait after each)
-    float4 v[kPer];
+template <int D>
+constexpr int tile_per() { return (32 * (D / 4) + kProtoThreads - 1) / kProtoThreads; }  // float4 per thread
+
+// A tile's rows loaded into registers, every load issued before any is used: an absent row
+// (rowof < 0) reads row 0 and is zeroed with a bit mask (a select would let the compiler put
+// the load behind a branch, with a wait after each).
+template <int D, typename RowOf>
+__device__ __forceinline__ void tile_load(const float *__restrict__ src, RowOf rowof, float4 (&v)[tile_per<D>()]) {
+    constexpr int Q = D / 4;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
+    for (int u = 0; u < tile_per<D>(); ++u) {
         const int e = threadIdx.x + u * kProtoThreads;
         const int i = min(e / Q, 31), q = e - (e / Q) * Q;
         const int64_t row = rowof(i);
@@ -96,11 +97,25 @@ __device__ __forceinline__ void stage_tile(float *tile, const float *__restrict_
         v[u] = make_float4(__int_as_float(__float_as_int(v[u].x) & m), __int_as_float(__float_as_int(v[u].y) & m),
                            __int_as_float(__float_as_int(v[u].z) & m), __int_as_float(__float_as_int(v[u].w) & m));
     }
+}
+
+template <int D>
+__device__ __forceinline__ void tile_store(float *tile, const float4 (&v)[tile_per<D>()]) {
+    constexpr int LD = D + 4, Q = D / 4;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
+    for (int u = 0; u < tile_per<D>(); ++u) {
         const int e = threadIdx.x + u * kProtoThreads;
         if (e < 32 * Q) *reinterpret_cast<float4 *>(tile + (e / Q) * LD + 4 * (e % Q)) = v[u];
     }
+}
+
+// Rows rowof(0..31) of src (D floats each; rowof < 0: zeros) into the LDS tile, rows padded
+// to D + 4 floats.
+template <int D, typename RowOf>
+__device__ __forceinline__ void stage_tile(float *tile, const float *__restrict__ src, RowOf rowof) {
+    float4 v[tile_per<D>()];
+    tile_load<D>(src, rowof, v);
+    tile_store<D>(tile, v);
 }
 
 // acc = sum_k tile[i][k] * fixed[j][k] for the 32 x 32 tile (i = tile row, j = lane column).
@@ -248,12 +263,22 @@ __global__ __launch_bounds__(kProtoThreads) void proto_fwd_kernel(ProtoIn in, co
     const int64_t ntiles = ceil_div(in.C, 32);
     const int64_t t0 = (int64_t)blockIdx.y * tiles_per_split, t1 = min(ntiles, t0 + tiles_per_split);
     float m = -INFINITY, s = 0.f, pos = -INFINITY;
+    // the next tile's rows are loaded into registers while the current one is multiplied
+    float4 nx[tile_per<D>()];
+    float nvalid = 0.f;
+    auto fetch = [&](int64_t t) {
+        const int64_t c0 = t * 32;
+        tile_load<D>(P, [&](int i) { return c0 + i < in.C ? c0 + i : (int64_t)-1; }, nx);
+        if (threadIdx.x < 32) nvalid = (c0 + threadIdx.x < in.C && inv[c0 + threadIdx.x] > 0.f) ? 1.f : 0.f;
+    };
+    if (t0 < t1) fetch(t0);
     for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
         const int64_t c0 = t * 32;
-        stage_tile<D>(tile, P, [&](int i) { return c0 + i < in.C ? c0 + i : (int64_t)-1; });
-        if (threadIdx.x < 32) tvalid[threadIdx.x] = (c0 + threadIdx.x < in.C && inv[c0 + threadIdx.x] > 0.f) ? 1.f : 0.f;
+        tile_store<D>(tile, nx);
+        if (threadIdx.x < 32) tvalid[threadIdx.x] = nvalid;
         __syncthreads();
+        if (t + 1 < t1) fetch(t + 1);
         const f32x16 acc = tile_product<D>(tile, r, j, h);
         float z[16], mt = -INFINITY;
 #pragma unroll
@@ -379,12 +404,21 @@ __global__ __launch_bounds__(kProtoThreads) void proto_bwd_rows_kernel(ProtoIn i
     for (int kb = 0; kb < D / 32; ++kb) out[kb] = f32x16{};
     const int64_t ntiles = ceil_div(in.C, 32);
     const int64_t t0 = (int64_t)blockIdx.y * tiles_per_split, t1 = min(ntiles, t0 + tiles_per_split);
+    float4 nx[tile_per<D>()];  // the next tile, loaded during the current one's products
+    float nvalid = 0.f;
+    auto fetch = [&](int64_t t) {
+        const int64_t c0 = t * 32;
+        tile_load<D>(P, [&](int i) { return c0 + i < in.C ? c0 + i : (int64_t)-1; }, nx);
+        if (threadIdx.x < 32) nvalid = (c0 + threadIdx.x < in.C && inv[c0 + threadIdx.x] > 0.f) ? 1.f : 0.f;
+    };
+    if (t0 < t1) fetch(t0);
     for (int64_t t = t0; t < t1; ++t) {
         __syncthreads();
         const int64_t c0 = t * 32;
-        stage_tile<D>(tile, P, [&](int i) { return c0 + i < in.C ? c0 + i : (int64_t)-1; });
-        if (threadIdx.x < 32) tvalid[threadIdx.x] = (c0 + threadIdx.x < in.C && inv[c0 + threadIdx.x] > 0.f) ? 1.f : 0.f;
+        tile_store<D>(tile, nx);
+        if (threadIdx.x < 32) tvalid[threadIdx.x] = nvalid;
         __syncthreads();
+        if (t + 1 < t1) fetch(t + 1);
         f32x16 g = tile_product<D>(tile, r, j, h);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
