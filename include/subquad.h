@@ -260,8 +260,10 @@ int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, i
  *   x = (s, c, e, |L_i - L_j|, [V_i == V_j]); z = W1 x + b1; g = W2 relu(z) + b2;
  *   w = softmax(g); fused[p] = sum_m w_m a_m; weights [P][3] (out, may be NULL): w.
  *   W1 [H][5], b1 [H], W2 [3][H], b2 [3] f32; H in {16, 32, 64}; d % 4 == 0, d <= 512.
- * The backward accumulates dW1, db1, dW2, db2 and (if non-NULL) demb exactly as
- * subquad_gate_bwd does; ws: subquad_gate3_bwd_workspace_bytes(H) bytes, 256-byte aligned.
+ * The backward accumulates dW1, db1, dW2, db2 (float64 per block, added into the workspace
+ * with atomics, so the last bits may vary between runs) and, if non-NULL, demb (float32
+ * atomics per pair), with the semantics of subquad_gate_bwd otherwise;
+ * ws: subquad_gate3_bwd_workspace_bytes(H) bytes, 256-byte aligned.
  */
 int subquad_gate3_fwd(const float *emb, int64_t n, int32_t d, const int32_t *lens,
                       const int32_t *vgene, const int32_t *self, const int32_t *pairs,
