@@ -320,3 +320,50 @@ def test_backward_sorted_and_shuffled_pairs_agree():
             ok, rel = grad_tol_ok(g.cpu().numpy(), ref[name])
             assert ok, (name, rel)
         assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(b.abs().max()))
+
+
+def test_gate_train_out_of_range_pairs():
+    """Pairs with an index outside [0, n) are skipped: their fused value is NaN and they add
+    nothing to the gradients, which equal those of the valid pairs alone (the mean loss
+    still divides by every pair, so those gradients are scaled by P_valid / P)."""
+    rep = synth.tiny(n_families=40, fam_size=8, seed=51)
+    c = make_case(rep, 128, 64, 1500, seed=51)
+    n = rep.n
+    bad = np.array([[n, 0], [0, n + 5], [-1, 3], [7, -2]], np.int32)
+    P = c["pairs"].shape[0]
+    mixed = dict(c, pairs=np.concatenate([c["pairs"], bad]), align=np.concatenate([c["align"], np.zeros(4, np.int32)]))
+    lab = dev(rep.family.astype(np.int32))
+    say("gate train with out-of-range pairs")
+    fused, loss, grads = sq.api.gate_train(*gpu_args(mixed), lab, 0.5)
+    f_ok, l_ok, g_ok = sq.api.gate_train(*gpu_args(c), lab, 0.5)
+    torch.cuda.synchronize()
+    f = fused.cpu().numpy()
+    assert np.isnan(f[P:]).all() and np.array_equal(f[:P], f_ok.cpu().numpy())
+    scale = P / (P + 4)
+    assert loss.item() == pytest.approx(l_ok.item() * scale, rel=1e-6)
+    for a, b in zip(grads, g_ok):
+        assert torch.allclose(a, b * scale, rtol=1e-5, atol=1e-7 * float(b.abs().max()))
+
+
+def test_gate_train_no_rows():
+    """n = 0 with pairs, through the C ABI with real (unused) row pointers: every pair is out
+    of range, the fused values are NaN and no gradient is formed (no row is read)."""
+    from paper_2602_17330_amd import _lib, api
+    rep = synth.tiny(seed=52)
+    c = make_case(rep, 64, 64, 50, seed=52)
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = gpu_args(c)
+    lab = dev(rep.family.astype(np.int32))
+    P, H = pairs.shape[0], W1.shape[0]
+    fused = torch.zeros(P, dtype=torch.float32, device="cuda")
+    loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda")
+    grads = [torch.zeros_like(t) for t in (W1, b1, w2, b2)]
+    ws = torch.empty(api.gate_bwd_workspace_bytes(H, P, 0), dtype=torch.uint8, device="cuda")
+    say("gate train n=0, P=50 (C ABI)")
+    api.check(_lib.lib().subquad_gate_train(
+        emb.data_ptr(), 0, 64, lens.data_ptr(), vgene.data_ptr(), self_s.data_ptr(), pairs.data_ptr(),
+        align_s.data_ptr(), P, W1.data_ptr(), b1.data_ptr(), w2.data_ptr(), b2.data_ptr(), H, lab.data_ptr(), 0.5,
+        fused.data_ptr(), loss.data_ptr(), *[g.data_ptr() for g in grads], None, ws.data_ptr(), ws.numel(),
+        torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert np.isnan(fused.cpu().numpy()).all() and loss.item() == 0.0
+    assert all(not g.any() for g in grads)
