@@ -484,9 +484,10 @@ def main():
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),
         # the fused gate pass, compulsory bytes: per pair its partner row, records and outputs,
-        # per distinct row its own row, gradient row in and gradient row out (rows by i in the
-        # first pass, rows by j in the second)
-        "gate_bwd_kernel": ("hbm", P * (4 * d + 16 + 4 + 8) + rows_i * (4 * d + 4 * d + 16)
+        # per distinct row its own row and its gradient row (rows by i in the first pass, which
+        # writes the gradient rows without reading them; rows by j in the second, which adds
+        # to them)
+        "gate_bwd_kernel": ("hbm", P * (4 * d + 16 + 4 + 8) + rows_i * (4 * d + 16)
                             + P * (16 + 16 + 4) + rows_i * 4 * d),
         "gate_cos_bwd_j_kernel": ("hbm", P * (8 + 16 + 4 + 4 * d) + rows_j * (4 * d + 4 * d)
                                   + rows_j * 4 * d),

@@ -241,6 +241,22 @@ int subquad_gate_train(const float *emb, int64_t n, int32_t d, const int32_t *le
                        float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * subquad_gate_train_set -- subquad_gate_train with the embedding gradient WRITTEN rather
+ * than accumulated: on return demb [n][d] holds d loss / d emb (rows of nodes in no pair
+ * are zero), so a training step needs no zero fill of demb first, and the first pass reads
+ * no old gradient rows.  demb's prior contents (NaN included) are never read.  The weight
+ * gradients, the loss and fused are as in subquad_gate_train (weight gradients ACCUMULATE).
+ * Same arguments, workspace and error codes.
+ */
+int subquad_gate_train_set(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                           const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                           const int32_t *align, int64_t P, const float *W1, const float *b1,
+                           const float *w2, const float *b2, int32_t H, const int32_t *label,
+                           float margin, float *fused, double *loss, float *dW1, float *db1,
+                           float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/*
  * subquad_edit_batch_ws -- the paper's own affinity recurrence (Appendix F.3), a weighted
  * global edit distance, on every pair:
  *   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost[a_x][b_y]),

@@ -40,6 +40,9 @@ SIGNATURES = {
     "subquad_gate_bwd_workspace_bytes": (c_sz, [c_i32, c_i64, c_i64]),
     "subquad_gate_train": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p, c_i32,
                                           c_p, ctypes.c_float, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "subquad_gate_train_set": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p,
+                                              c_i32, c_p, ctypes.c_float, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz,
+                                              c_p]),
     "subquad_gate_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "subquad_edit_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p, c_sz,

@@ -210,9 +210,10 @@ def gate_bwd(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, grad_fuse
 
 
 def gate_train(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, labels, margin: float = 0.5,
-               fused=None, loss=None, grads=None, ws: torch.Tensor | None = None):
+               fused=None, loss=None, grads=None, ws: torch.Tensor | None = None, set_demb: bool = False):
     """Fused forward + contrastive loss + backward.  Returns (fused, loss, (dW1, db1, dw2, db2, demb));
-    gradients accumulate into ``grads`` when given."""
+    gradients accumulate into ``grads`` when given, except that with ``set_demb`` the
+    embedding gradient is written (no zero fill needed)."""
     emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = _gate_args(
         emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
     labels = _dev(labels, torch.int32, "labels")
@@ -225,10 +226,10 @@ def gate_train(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, labels,
     need = gate_bwd_workspace_bytes(H, P, emb.shape[0])
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
-    check(lib().subquad_gate_train(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s),
-                                   _ptr(pairs), _ptr(align_s), P, _ptr(W1), _ptr(b1), _ptr(w2), _ptr(b2), H,
-                                   _ptr(labels), margin, _ptr(fused), _ptr(loss), *[_ptr(g) for g in grads],
-                                   _ptr(ws), ws.numel(), _stream()))
+    fn = lib().subquad_gate_train_set if set_demb else lib().subquad_gate_train
+    check(fn(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s), _ptr(pairs),
+             _ptr(align_s), P, _ptr(W1), _ptr(b1), _ptr(w2), _ptr(b2), H, _ptr(labels), margin, _ptr(fused),
+             _ptr(loss), *[_ptr(g) for g in grads], _ptr(ws), ws.numel(), _stream()))
     return fused, loss, grads
 
 

@@ -254,8 +254,8 @@ struct TrainOut {
     float margin, inv_P;
     float *fused;
     double *loss_partial;
+    bool set_demb;  // demb is written, not accumulated (rows without pairs are zeroed)
 };
-
 
 // First pass of the backward, over the pairs in order of their first index i (order_i: the
 // records (i << 32 | p) sorted, or in their natural order when the pairs are sorted already):
@@ -341,7 +341,14 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                 cur_i = i;
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
-                if (demb) load_grad_row<NV>(demb, i, d4, l, old);
+                if (demb) {
+                    if (tr.set_demb) {  // written, not added to: the row's old value counts as zero
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) old[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    } else {
+                        load_grad_row<NV>(demb, i, d4, l, old);
+                    }
+                }
                 ni = in.node[i];
                 load_row_norm<NV>(in, i, d4, l, ei, ni2);
             }
@@ -617,6 +624,42 @@ struct GateOrders {
     const int64_t *unsorted;    // [0]: 1 when the pairs are not in order of i, [1]: records the i sort takes
 };
 
+__global__ void fill_f32_kernel(float *__restrict__ x, int64_t count, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+// For a first pass that writes demb rather than adding to it: the rows it does not write are
+// set to zero beforehand.  The i keys are in order (sorted, or the natural order the in-order
+// check accepted), so the rows with no pair are the gaps between consecutive keys; and a row
+// whose records straddle the start of a lane group's chunk (q = g * chunk) is added to
+// atomically from both sides, so it starts from zero.  One 16-lane group per record q in
+// [0, P]: it zeroes the gap rows (key[q-1], key[q]) (with key[-1] = -1 and key[P] = n) and,
+// at a chunk start, the straddling row.
+__global__ __launch_bounds__(256) void gate_set_rows_prep_kernel(const uint64_t *__restrict__ order_nat,
+                                                                 const uint64_t *__restrict__ order_sorted,
+                                                                 const int64_t *__restrict__ unsorted, int64_t P,
+                                                                 int64_t n, int64_t chunk, int d4,
+                                                                 float *__restrict__ demb) {
+    const uint64_t *order_i = unsorted[0] == 0 ? order_nat : order_sorted;
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / kGroup);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup; q <= P; q += ngroups) {
+        const int64_t ka = q == 0 ? -1 : (int64_t)(order_i[q - 1] >> 32);
+        const int64_t kb = q == P ? n : (int64_t)(order_i[q] >> 32);
+        const int64_t a = ka < n ? ka : n, b = kb < n ? kb : n;
+        for (int64_t r = a + 1; r < b; ++r) {
+            float4 *row = reinterpret_cast<float4 *>(demb) + r * d4;
+            for (int c = l; c < d4; c += kGroup) row[c] = z;
+        }
+        if (q > 0 && q < P && q % chunk == 0 && a == b && b < n) {
+            float4 *row = reinterpret_cast<float4 *>(demb) + b * d4;
+            for (int c = l; c < d4; c += kGroup) row[c] = z;
+        }
+    }
+}
+
 template <int NV, bool TRAIN>
 static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, int64_t *lblocks, const GateOrders &o,
                        float4 *pack, float4 *feat, float *demb, double *wpart, float *dW1, float *db1, float *dw2,
@@ -628,6 +671,13 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
         {                                                                                                          \
             const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U, TRAIN>);                 \
             if (lblocks) *lblocks = blocks;                                                                        \
+            if (demb && tr.set_demb) {                                                                             \
+                const int64_t chunk = ceil_div(in.P, blocks * (kGateThreads / kGroup));                           \
+                const int64_t pblocks = std::min<int64_t>(ceil_div(in.P + 1, 256 / kGroup), gate_max_blocks() * 8);  \
+                gate_set_rows_prep_kernel<<<(unsigned)pblocks, 256, 0, st>>>(o.order_nat, o.order_i, o.unsorted, in.P, \
+                                                                             in.n, chunk, in.d >> 2, demb);        \
+                SQ_LAUNCHED("gate_set_rows_prep_kernel");                                                          \
+            }                                                                                                      \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
             gate_bwd_kernel<NV, U, TRAIN><<<(unsigned)blocks, kGateThreads, 0, st>>>(                                \
                 in, gf, o.order_nat, o.order_i, o.unsorted, pack, feat, demb, tr);                                \
@@ -829,7 +879,7 @@ extern "C" size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P, int64_t
 template <bool TRAIN>
 static int gate_backward(const GateIn &in0, const int32_t *label, const float *grad_fused, float margin, float *fused,
                          double *loss, float *dW1, float *db1, float *dw2, float *db2, float *demb, void *ws,
-                         size_t ws_bytes, void *stream) {
+                         size_t ws_bytes, void *stream, bool set_demb = false) {
     GateIn in = in0;
     int rc = gate_validate(in);
     if (rc != SUBQUAD_OK) return rc;
@@ -855,6 +905,11 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
             contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, 0, 0, loss);
             SQ_LAUNCHED("contrastive_final_kernel");
         }
+        if (set_demb && demb && in.n > 0) {  // no pairs: the written gradient is zero
+            fill_f32_kernel<<<(unsigned)std::min<int64_t>(ceil_div(in.n * in.d, 256), (int64_t)device_cus() * 16), 256,
+                              0, st>>>(demb, in.n * (int64_t)in.d, 0.f);
+            SQ_LAUNCHED("fill_f32_kernel");
+        }
         return SUBQUAD_OK;
     }
     double *wpart = reinterpret_cast<double *>(w + L.wpart);
@@ -870,7 +925,7 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
     if (rc != SUBQUAD_OK) return rc;
     float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
     float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
-    const TrainOut tr{margin, 1.f / (float)in.P, fused, lpart};
+    const TrainOut tr{margin, 1.f / (float)in.P, fused, lpart, set_demb};
     int64_t lblocks = 0;
     const int nv = (int)ceil_div(in.d / 4, kGroup);
     if (nv <= 1) rc = gate_bwd_nv<1, TRAIN>(in, grad_fused, tr, &lblocks, orders, pack, feat, demb, wpart, dW1, db1, dw2,
@@ -911,6 +966,18 @@ extern "C" int subquad_gate_train(const float *emb, int64_t n, int32_t d, const 
     clear_error();
     const GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H, nullptr};
     return gate_backward<true>(in, label, nullptr, margin, fused, loss, dW1, db1, dw2, db2, demb, ws, ws_bytes, stream);
+}
+
+extern "C" int subquad_gate_train_set(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                                      const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                                      const int32_t *align, int64_t P, const float *W1, const float *b1,
+                                      const float *w2, const float *b2, int32_t H, const int32_t *label, float margin,
+                                      float *fused, double *loss, float *dW1, float *db1, float *dw2, float *db2,
+                                      float *demb, void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    const GateIn in{emb, n, d, lens, vgene, self, pairs, align, P, W1, b1, w2, b2, H, nullptr};
+    return gate_backward<true>(in, label, nullptr, margin, fused, loss, dW1, db1, dw2, db2, demb, ws, ws_bytes, stream,
+                               true);
 }
 
 extern "C" size_t subquad_contrastive_workspace_bytes(void) { return sizeof(double) * (size_t)contrastive_blocks(); }

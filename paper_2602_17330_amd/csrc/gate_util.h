@@ -228,12 +228,16 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     }
 }
 
-// Records (key << 32 | p) for the pair-order sorts: key = pairs[p][side].
+// Records (key << 32 | p) for the pair-order sorts: key = pairs[p][side], or n for a pair
+// with either index out of range (such pairs sort last on both sides; the same key as the
+// in-order check of the pairs gives them, so that a natural order passed by that check is
+// in order of these keys too).
 static __global__ void gate_order_keys_kernel(const int32_t *__restrict__ pairs, int64_t P, int64_t n, int side,
                                        uint64_t *__restrict__ rec) {
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = pairs[2 * p + side];
-        const uint64_t key = (k < 0 || k >= n) ? (uint64_t)n : (uint64_t)k;  // out of range sorts last
+        const int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+        const bool ok = i >= 0 && i < n && j >= 0 && j < n;
+        const uint64_t key = ok ? (uint64_t)(side ? j : i) : (uint64_t)n;
         rec[p] = (key << 32) | (uint64_t)p;
     }
 }

@@ -128,12 +128,14 @@ class Pipeline:
             self.loss_grad()
             self.gate_bwd()
             return
-        for g in self.grads:
+        for g in self.grads[:4]:  # the embedding gradient is written by the training pass itself
             g.zero_()
         P = self.P
         if P:
             api.gate_train(*self.gate_args(), self.family, self.cfg.margin, fused=self.fused[:P], loss=self.loss,
-                           grads=tuple(self.grads), ws=self.gate_ws)
+                           grads=tuple(self.grads), ws=self.gate_ws, set_demb=True)
+        else:
+            self.grads[4].zero_()
 
     def lsh_async(self):
         """Graph-capturable candidate stage: no host synchronisation; the pair sort is sized

@@ -296,6 +296,12 @@ def test_gate_train_empty():
     fused, loss, grads = sq.api.gate_train(*gpu_args(c), dev(rep.family.astype(np.int32)), 0.5)
     torch.cuda.synchronize()
     assert fused.shape == (0,) and loss.item() == 0.0 and not grads[4].any()
+    # the writing variant with no pairs: every gradient row is written as zero
+    g2 = tuple(torch.zeros_like(g) for g in grads[:4]) + (torch.full_like(grads[4], float("nan")),)
+    say("gate train P=0, demb written")
+    _, loss2, g2 = sq.api.gate_train(*gpu_args(c), dev(rep.family.astype(np.int32)), 0.5, grads=g2, set_demb=True)
+    torch.cuda.synchronize()
+    assert loss2.item() == 0.0 and not g2[4].isnan().any() and not g2[4].any()
 
 
 def test_backward_sorted_and_shuffled_pairs_agree():
@@ -367,3 +373,38 @@ def test_gate_train_no_rows():
     torch.cuda.synchronize()
     assert np.isnan(fused.cpu().numpy()).all() and loss.item() == 0.0
     assert all(not g.any() for g in grads)
+
+
+@pytest.mark.parametrize("P,sorted_pairs", [(3000, False), (3000, True), (40000, True), (40000, False)])
+def test_gate_train_set_writes_demb(P, sorted_pairs):
+    """The writing training pass: demb starts as NaN and ends equal to the accumulating pass
+    on a zeroed buffer (rows without pairs zero, rows split between chunks complete), with
+    out-of-range pairs mixed in: one with i out of range, one with j out of range on a row
+    that has pairs, and one on a row that has none.  Sorted pairs are walked in their own
+    order (the out-of-range ones after the rest), shuffled ones through the sort."""
+    rep = synth.tiny(n_families=80, fam_size=10, seed=60 + P)
+    c = make_case(rep, 128, 64, P, seed=60)
+    order = np.lexsort((c["pairs"][:, 1], c["pairs"][:, 0]))
+    if not sorted_pairs:
+        order = np.random.default_rng(P).permutation(len(order))
+    c = dict(c, pairs=np.ascontiguousarray(c["pairs"][order]), align=np.ascontiguousarray(c["align"][order]))
+    n = rep.n
+    lone = int(np.setdiff1d(np.arange(n), c["pairs"][:, 0])[0])  # a row with no pair as i
+    bad = np.array([[n, 0], [2, n + 1], [lone, -1]], np.int32)
+    c = dict(c, pairs=np.concatenate([c["pairs"], bad]), align=np.concatenate([c["align"], np.zeros(3, np.int32)]))
+    lab = dev(rep.family.astype(np.int32))
+    args = gpu_args(c)
+    say(f"gate train, demb written (P={P}, sorted={sorted_pairs})")
+    f1, l1, g1 = sq.api.gate_train(*args, lab, 0.5)
+    g2 = tuple(torch.zeros_like(g) for g in g1[:4]) + (torch.full_like(g1[4], float("nan")),)
+    f2, l2, g2 = sq.api.gate_train(*args, lab, 0.5, grads=g2, set_demb=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(f1, nan=-7.0), torch.nan_to_num(f2, nan=-7.0))
+    assert l1.item() == l2.item()
+    assert not torch.isnan(g2[4]).any()
+    touched = np.zeros(n, bool)
+    ok = (c["pairs"] >= 0).all(axis=1) & (c["pairs"] < n).all(axis=1)
+    touched[c["pairs"][ok].ravel()] = True
+    assert not g2[4][torch.from_numpy(~touched).cuda()].any()
+    for a, b in zip(g1, g2):
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(a.abs().max()))
