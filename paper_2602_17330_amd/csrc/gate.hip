@@ -633,29 +633,43 @@ __global__ void fill_f32_kernel(float *__restrict__ x, int64_t count, float v) {
 // set to zero beforehand.  The i keys are in order (sorted, or the natural order the in-order
 // check accepted), so the rows with no pair are the gaps between consecutive keys; and a row
 // whose records straddle the start of a lane group's chunk (q = g * chunk) is added to
-// atomically from both sides, so it starts from zero.  One 16-lane group per record q in
-// [0, P]: it zeroes the gap rows (key[q-1], key[q]) (with key[-1] = -1 and key[P] = n) and,
-// at a chunk start, the straddling row.
+// atomically from both sides, so it starts from zero.  One lane per record q in [0, P]
+// finds its rows to zero: the gap (key[q-1], key[q]) (with key[-1] = -1, key[P] = n), or at
+// a chunk start the straddling row; then the whole wave zeroes each lane's rows in turn with
+// contiguous stores.
 __global__ __launch_bounds__(256) void gate_set_rows_prep_kernel(const uint64_t *__restrict__ order_nat,
                                                                  const uint64_t *__restrict__ order_sorted,
                                                                  const int64_t *__restrict__ unsorted, int64_t P,
                                                                  int64_t n, int64_t chunk, int d4,
                                                                  float *__restrict__ demb) {
     const uint64_t *order_i = unsorted[0] == 0 ? order_nat : order_sorted;
-    const int l = threadIdx.x & (kGroup - 1);
-    const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / kGroup);
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kGroup; q <= P; q += ngroups) {
-        const int64_t ka = q == 0 ? -1 : (int64_t)(order_i[q - 1] >> 32);
-        const int64_t kb = q == P ? n : (int64_t)(order_i[q] >> 32);
-        const int64_t a = ka < n ? ka : n, b = kb < n ? kb : n;
-        for (int64_t r = a + 1; r < b; ++r) {
-            float4 *row = reinterpret_cast<float4 *>(demb) + r * d4;
-            for (int c = l; c < d4; c += kGroup) row[c] = z;
+    float4 *__restrict__ rows = reinterpret_cast<float4 *>(demb);
+    // q0 is the same for every lane of a wave, so all lanes run the same iterations
+    for (int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 64; q0 <= P; q0 += nwaves * 64) {
+        const int64_t q = q0 + lane;
+        int64_t lo = 0, hi = 0;  // rows [lo, hi) to zero
+        if (q <= P) {
+            const int64_t ka = q == 0 ? -1 : (int64_t)(order_i[q - 1] >> 32);
+            const int64_t kb = q == P ? n : (int64_t)(order_i[q] >> 32);
+            const int64_t a = ka < n ? ka : n, b = kb < n ? kb : n;
+            lo = a + 1;
+            hi = b;
+            if (q > 0 && q < P && q % chunk == 0 && a == b && b < n) {  // the straddling row
+                lo = b;
+                hi = b + 1;
+            }
         }
-        if (q > 0 && q < P && q % chunk == 0 && a == b && b < n) {
-            float4 *row = reinterpret_cast<float4 *>(demb) + b * d4;
-            for (int c = l; c < d4; c += kGroup) row[c] = z;
+        uint64_t todo = __ballot(hi > lo);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const int64_t rlo = __shfl(lo, src), rhi = __shfl(hi, src);
+            float4 *__restrict__ dst = rows + rlo * d4;
+            const int64_t count = (rhi - rlo) * d4;
+            for (int64_t e = lane; e < count; e += 64) dst[e] = z;
         }
     }
 }
@@ -673,7 +687,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
             if (lblocks) *lblocks = blocks;                                                                        \
             if (demb && tr.set_demb) {                                                                             \
                 const int64_t chunk = ceil_div(in.P, blocks * (kGateThreads / kGroup));                           \
-                const int64_t pblocks = std::min<int64_t>(ceil_div(in.P + 1, 256 / kGroup), gate_max_blocks() * 8);  \
+                const int64_t pblocks = std::min<int64_t>(ceil_div(in.P + 1, 256), gate_max_blocks() * 4);          \
                 gate_set_rows_prep_kernel<<<(unsigned)pblocks, 256, 0, st>>>(o.order_nat, o.order_i, o.unsorted, in.P, \
                                                                              in.n, chunk, in.d >> 2, demb);        \
                 SQ_LAUNCHED("gate_set_rows_prep_kernel");                                                          \
