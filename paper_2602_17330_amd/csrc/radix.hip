@@ -39,8 +39,12 @@ __device__ __forceinline__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *w
     return v + add;
 }
 
+// (live, when given, is a record count on the device: with none, the scan has nothing to do
+// and each of its kernels returns at once; the whole block takes the same branch.)
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ data,
-                                                                   int64_t count, uint32_t *__restrict__ partial) {
+                                                                   int64_t count, uint32_t *__restrict__ partial,
+                                                                   const int64_t *__restrict__ live) {
+    if (live && *live <= 0) return;
     __shared__ uint32_t wt[4];
     int64_t base = (int64_t)blockIdx.x * kScanChunk;
     uint32_t v[kScanItems], s = 0;
@@ -54,7 +58,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
 }
 
 // Single block: exclusive scan of the chunk totals, any length.
-__global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *__restrict__ partial, int64_t m) {
+__global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *__restrict__ partial, int64_t m,
+                                                                     const int64_t *__restrict__ live) {
+    if (live && *live <= 0) return;
     __shared__ uint32_t wt[4];
     __shared__ uint32_t carry_s;
     if (threadIdx.x == 0) carry_s = 0;
@@ -72,7 +78,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *_
 }
 
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ data, int64_t count,
-                                                                  const uint32_t *__restrict__ partial) {
+                                                                  const uint32_t *__restrict__ partial,
+                                                                  const int64_t *__restrict__ live) {
+    if (live && *live <= 0) return;
     __shared__ uint32_t wt[4];
     // thread t owns kScanItems consecutive entries
     int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
@@ -99,17 +107,22 @@ size_t scan_scratch_bytes(int64_t count) {
     return align_up(sizeof(uint32_t) * (size_t)std::max<int64_t>(1, ceil_div(count, kScanChunk)), 256);
 }
 
-int scan_exclusive_u32(uint32_t *data, int64_t count, void *scratch, hipStream_t st) {
+static int scan_exclusive_u32_live(uint32_t *data, int64_t count, const int64_t *live, void *scratch,
+                                   hipStream_t st) {
     if (count <= 0) return SUBQUAD_OK;
     int64_t chunks = ceil_div(count, kScanChunk);
     uint32_t *partial = static_cast<uint32_t *>(scratch);
-    scan_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial);
+    scan_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
     SQ_LAUNCHED("scan_reduce_kernel");
-    scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks);
+    scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks, live);
     SQ_LAUNCHED("scan_partials_kernel");
-    scan_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial);
+    scan_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
     SQ_LAUNCHED("scan_apply_kernel");
     return SUBQUAD_OK;
+}
+
+int scan_exclusive_u32(uint32_t *data, int64_t count, void *scratch, hipStream_t st) {
+    return scan_exclusive_u32_live(data, count, nullptr, scratch, st);
 }
 
 // ---- 64-bit exclusive scan (device-side element count) ----
@@ -227,6 +240,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_
                                                                    int64_t nblocks) {
     __shared__ uint32_t h[kRadixBuckets];
     const int64_t n = live_count(n_cap, n_dev);
+    if (n_dev && n == 0) return;  // no records: the scan and the scatter skip this pass too
     h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
@@ -363,7 +377,7 @@ int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev
         int rc;
         {
             ProfScope prof(scan_name.c_str(), st);
-            rc = scan_exclusive_u32(hist, hist_n, scan_scratch, st);
+            rc = scan_exclusive_u32_live(hist, hist_n, n_dev, scan_scratch, st);
         }
         if (rc != SUBQUAD_OK) return rc;
         {
