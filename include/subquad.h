@@ -208,8 +208,8 @@ size_t subquad_gate_bwd_workspace_bytes(int32_t H, int64_t P, int64_t n);
  * storing it.  Gradients ACCUMULATE into the outputs (zero them first for a plain
  * gradient): dW1 [H][4], db1 [H], dw2 [H], db2 [1], demb [n][d] (may be NULL: then the
  * embedding gradient is skipped).  The alignment, length and V-gene inputs get no gradient.
- * Weight gradients are reduced in float64, per block and then over blocks in a fixed order
- * (reproducible bit for bit).  The embedding gradient is gathered in two
+ * Weight gradients are summed in float32 over each run of 16 consecutive pairs, then in
+ * float64 per block and over blocks in a fixed order (reproducible bit for bit).  The embedding gradient is gathered in two
  * passes over the pairs, stably sorted by i and then by j: a row whose pairs all fall in one
  * worker's chunk is updated with a plain read-modify-write, a row split between chunks with
  * float32 atomics (summation order, and last bits, may then vary between runs).  demb must

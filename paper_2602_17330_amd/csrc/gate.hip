@@ -461,7 +461,9 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
 // pair, no gathers): with ubar = dL/du and z = W1 x + b1 recomputed from x,
 //   dW1[k] += ubar w2_k [z_k > 0] x,  db1[k] += ubar w2_k [z_k > 0],
 //   dw2[k] += ubar relu(z_k),          db2 += ubar.
-// Lane l of a 16-lane group owns units l + 16 m; float64 accumulators, reduced per block
+// Lane l of a 16-lane group owns units l + 16 m; each batch of 16 pairs is summed in
+// float32 and added to float64 accumulators (a sixteenth of the float64 adds of one per
+// term, which bound this kernel), reduced per block
 // into column-major partials wpart[col][block] over the 6H + 1 values (dW1[H][4], db1[H],
 // dw2[H], db2), which gate_ws_reduce_kernel sums in a fixed order (no atomics: the weight
 // gradients are reproducible bit for bit).
@@ -490,6 +492,16 @@ __global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, con
         const float4 f = mine < p1 ? feat[mine] : make_float4(0.f, 0.f, 0.f, 0.f);
         const float ub = mine < p1 ? pack[mine].w : 0.f;
         const int cnt = (int)min((int64_t)kGroup, p1 - pb);
+        // the batch's (at most 16) terms are summed in float32, then added to the float64
+        // accumulators once per batch
+        float fW1[UNITS][4], fb1[UNITS], fw2[UNITS], fb2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < UNITS; ++k) {
+            fb1[k] = 0.f;
+            fw2[k] = 0.f;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) fW1[k][qq] = 0.f;
+        }
         for (int t = 0; t < cnt; ++t) {
             const float s = __shfl(f.x, t, kGroup), c = __shfl(f.y, t, kGroup);
             const float x2 = __shfl(f.z, t, kGroup), x3 = __shfl(f.w, t, kGroup);
@@ -498,14 +510,22 @@ __global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, con
 #pragma unroll
             for (int k = 0; k < UNITS; ++k) {
                 const float z = unit_preact(W1[k], b1[k], s, c, x2, x3);
-                aw2[k] += (double)(ubar * fmaxf(z, 0.f));
+                fw2[k] = fmaf(ubar, fmaxf(z, 0.f), fw2[k]);
                 const float zbar = z > 0.f ? ubar * w2[k] : 0.f;
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq) aW1[k][qq] += (double)(zbar * x[qq]);
-                ab1[k] += (double)zbar;
+                for (int qq = 0; qq < 4; ++qq) fW1[k][qq] = fmaf(zbar, x[qq], fW1[k][qq]);
+                fb1[k] += zbar;
             }
-            if (l == 0) ab2 += (double)ubar;
+            fb2 += ubar;
         }
+#pragma unroll
+        for (int k = 0; k < UNITS; ++k) {
+            aw2[k] += (double)fw2[k];
+            ab1[k] += (double)fb1[k];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) aW1[k][qq] += (double)fW1[k][qq];
+        }
+        if (l == 0) ab2 += (double)fb2;
     }
 
     // Block reduction: lanes with equal l hold the same units.
