@@ -111,3 +111,34 @@ def test_self_estimate_is_one():
     T = mh.hash_tables(synth.HASH_SEED, 64)
     s = [1, 5, 9, 2, 2, 7]
     assert mh.jaccard_estimate(mh.signature(s, T), mh.signature(s, T)) == 1.0
+
+
+@pytest.mark.parametrize("M", [1, 64, 65, 128, 256])
+@pytest.mark.parametrize("stride", [4, 8, 20, 32, 64])
+def test_c_loop_matches_set_definition(M, stride):
+    """The C loop (minhash_ref.c) against the set-based definition and the vectorised form,
+    on edge lengths 3 and stride, repeated 3-mers and ragged rows."""
+    rng = np.random.default_rng(1000 + 7 * M + stride)
+    n = 24
+    lens = rng.integers(3, stride + 1, n).astype(np.int32)
+    lens[0], lens[1] = 3, stride
+    seqs = np.full((n, stride), 0xFF, dtype=np.uint8)
+    for i in range(n):
+        seqs[i, : lens[i]] = rng.integers(0, 20, lens[i])
+    if stride >= 9:
+        lens[2] = 9
+        seqs[2, :9] = [4, 7, 1] * 3        # one shingle repeated (set of 3 distinct)
+    T = mh.hash_tables(synth.HASH_SEED, M)
+    c = mh.signatures_c(seqs, lens, M, synth.HASH_SEED)
+    v = mh.signatures(seqs, lens, M, synth.HASH_SEED)
+    assert c.dtype == np.uint64 and c.shape == (n, M)
+    assert np.array_equal(c, v)
+    for i in range(n):
+        assert np.array_equal(c[i], mh.signature(seqs[i, : lens[i]], T))
+
+
+def test_c_loop_matches_vectorised_small5k():
+    r = synth.small5k()
+    M = r.params["M"]
+    assert np.array_equal(mh.signatures_c(r.seqs, r.lens, M, synth.HASH_SEED),
+                          mh.signatures(r.seqs, r.lens, M, synth.HASH_SEED))
