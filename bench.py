@@ -280,50 +280,143 @@ def rmt_leg(torch, sq, pipe):
                                "frac": ach / HBM_PEAK_GBS if ach else None, "alg_bytes_per_launch": alg})
 
 
-def cpu_baseline(rep, emb, S, pipe, cfg):
-    """The oracle, untouched, on a bounded sample of the same workload; each stage's time
-    is scaled linearly to the full workload (per sequence, per cell, per pair)."""
-    from oracle import gate as ogate
-    from oracle import lsh as olsh
+# Inputs of the CPU-baseline workers: set before the pool forks, so every task carries only
+# an index or a slice bound, never the tables.
+_CPU: dict = {}
+
+
+def _cpu_minhash(bounds):
+    """Signatures of rows lo..hi, written into the shared output mapping."""
     from oracle import minhash as omh
+    lo, hi = bounds
+    d = _CPU
+    d["sig"][lo:hi] = omh.signatures_c(d["seqs"][lo:hi], d["lens"][lo:hi], d["M"], d["seed"])
+
+
+def _cpu_lsh_band(beta):
+    """Candidate keys lo * n + hi of one band (the oracle's grouping on that band's rows)."""
+    from oracle import lsh as olsh
+    d = _CPU
+    r = d["r"]
+    c = olsh.candidates_grouped(np.ascontiguousarray(d["sig"][:, beta * r:(beta + 1) * r]), 1, r)
+    return c[:, 0] * d["sig"].shape[0] + c[:, 1]
+
+
+def _cpu_sw(bounds):
     from oracle import sw as osw
+    lo, hi = bounds
+    d = _CPU
+    return osw.scores_pairs(d["seqs"], d["lens"], d["pairs"][lo:hi], d["S"], d["go"], d["ge"])
+
+
+def _cpu_gate(bounds):
+    """Gate forward + backward of one chunk of pairs on the rows it touches."""
+    from oracle import gate as ogate
+    lo, hi = bounds
+    d = _CPU
+    pr = d["pairs"][lo:hi]
+    rows, inv = np.unique(pr.ravel(), return_inverse=True)
+    loc = inv.reshape(-1, 2)
+    g = ogate.backward(d["emb"][rows], d["lens"][rows], d["vgene"][rows], d["self"][rows], loc,
+                       d["align"][lo:hi], *d["W"], d["gf"][lo:hi])
+    return rows, g["emb"][: rows.shape[0]], [g[k] for k in ("W1", "b1", "w2", "b2")]
+
+
+def _cpu_worker_init():
+    """One BLAS/OpenMP thread per worker process: ``cores`` processes use ``cores`` cores."""
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
+
+
+def _chunks(n, parts):
+    edges = np.linspace(0, n, parts + 1).astype(np.int64)
+    return [(int(a), int(b)) for a, b in zip(edges[:-1], edges[1:]) if b > a]
+
+
+def cpu_baseline(rep, emb, S, pipe, cfg):
+    """The oracle, untouched, timed on the host cores over the same workload.
+
+    MinHash (C loop) and LSH (numpy grouping, one task per band, then the union) run on
+    every sequence; Smith-Waterman (C) and the gate forward + backward (numpy float64) run
+    on seeded samples of the oracle's own candidate pairs, their times scaled linearly to
+    the full workload (DP cells, pairs).  Work is split over a fork pool of ``cores``
+    processes; a single-process Smith-Waterman run on part of the sample gives the per-core
+    rate beside it."""
+    import mmap
+    import multiprocessing as mp
     import synth
+    from oracle import sw as osw
     cores = min(16, len(os.sched_getaffinity(0)))
     n = rep.n
-    ns = min(n, 100_000)
-    rows = np.arange(ns)
+    _CPU.clear()
+    _CPU.update(seqs=np.ascontiguousarray(rep.seqs), lens=np.ascontiguousarray(rep.lens, dtype=np.int32),
+                M=cfg.M, seed=synth.HASH_SEED, r=cfg.r, S=np.ascontiguousarray(S, dtype=np.int8),
+                go=cfg.gap_open, ge=cfg.gap_extend)
+    osw.build()
+    ctx = mp.get_context("fork")
+    stage = {}
+    # the signatures land in an anonymous shared mapping that the forked workers write
+    sig_map = mmap.mmap(-1, max(1, n * cfg.M * 8))
+    _CPU["sig"] = np.frombuffer(sig_map, dtype=np.uint64, count=n * cfg.M).reshape(n, cfg.M)
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        t = time.perf_counter()
+        pool.map(_cpu_minhash, _chunks(n, cores * 4))
+        stage["minhash"] = time.perf_counter() - t
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        t = time.perf_counter()
+        keys = pool.map(_cpu_lsh_band, range(cfg.b))
+        allk = np.unique(np.concatenate(keys))
+        cand = np.stack([allk // n, allk % n], axis=1).astype(np.int32)
+        stage["lsh"] = time.perf_counter() - t
+    del keys, allk
+    P_oracle = int(cand.shape[0])
+    Ps = min(P_oracle, 2_000_000)
+    ps = np.ascontiguousarray(cand[np.sort(synth.sample_rows(P_oracle, Ps, 3))])
+    L = rep.lens.astype(np.int64)
+    cells_s = int((L[ps[:, 0]] * L[ps[:, 1]]).sum())
+    _CPU["pairs"] = ps
+    # one core, on the first 5% of the sample
+    P1 = max(1, Ps // 20)
+    cells_1 = int((L[ps[:P1, 0]] * L[ps[:P1, 1]]).sum())
     t = time.perf_counter()
-    sig_s = omh.signatures_c(rep.seqs[rows], rep.lens[rows], cfg.M, synth.HASH_SEED)
-    t_mh = (time.perf_counter() - t) * n / ns
-    t = time.perf_counter()
-    cand_s = olsh.candidates_grouped(sig_s, cfg.b, cfg.r)
-    t_lsh = (time.perf_counter() - t) * n / ns
-    # the alignment and gate samples are the oracle's own candidates on that subset
-    Ps = min(cand_s.shape[0], 300_000)
-    ps = cand_s[synth.sample_rows(cand_s.shape[0], Ps, 3)].astype(np.int32)
-    cells_s = int((rep.lens[ps[:, 0]].astype(np.int64) * rep.lens[ps[:, 1]]).sum())
-    t = time.perf_counter()
-    al = osw.scores_pairs_parallel(rep.seqs, rep.lens, ps, S, cfg.gap_open, cfg.gap_extend, procs=cores)
-    t_sw_s = time.perf_counter() - t
-    P = pipe.P
-    cells = pipe.cells()  # size of the full workload, used only to scale the sample time
-    t_sw = t_sw_s * cells / max(cells_s, 1)
+    osw.scores_pairs(rep.seqs, rep.lens, ps[:P1], S, cfg.gap_open, cfg.gap_extend)
+    sw_1core = cells_1 / (time.perf_counter() - t) / 1e9     # (the C loop is single-threaded)
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        t = time.perf_counter()
+        al = np.concatenate(pool.map(_cpu_sw, _chunks(Ps, cores * 4)))
+        t_sw_s = time.perf_counter() - t
     self_s = osw.self_scores(rep.seqs, rep.lens, S)
-    W1, b1, w2, b2 = synth.gate_params(64)
-    Pg = min(Ps, 100_000)
-    pg = ps[:Pg]
-    gf = synth.upstream_grad(Pg)
-    t = time.perf_counter()
-    ogate.backward(emb, rep.lens, rep.vgene, self_s, pg, al[:Pg], W1, b1, w2, b2, gf)
-    t_gate = (time.perf_counter() - t) * P / Pg
-    total = t_mh + t_lsh + t_sw + t_gate
+    Pg = min(Ps, 250_000)
+    _CPU.update(emb=emb, vgene=rep.vgene, self=self_s, align=al, W=synth.gate_params(64),
+                gf=synth.upstream_grad(Ps), pairs=ps)
+    with ctx.Pool(cores, initializer=_cpu_worker_init) as pool:
+        t = time.perf_counter()
+        parts = pool.map(_cpu_gate, _chunks(Pg, cores * 4))
+        dW = [sum(p[2][k] for p in parts) for k in range(4)]
+        rows = np.unique(np.concatenate([p[0] for p in parts]))
+        dE = np.zeros((rows.shape[0], emb.shape[1]))
+        for rr, g, _ in parts:       # rows are unique within a chunk
+            dE[np.searchsorted(rows, rr)] += g
+        t_gate_s = time.perf_counter() - t
+    del parts, dE, dW
+    _CPU.clear()
+    sig_map.close()
+    P = pipe.P
+    cells = pipe.cells()  # size of the GPU step's workload, used only to scale the sample times
+    stage["align"] = t_sw_s * cells / max(cells_s, 1)
+    stage["gate"] = t_gate_s * P / Pg
+    total = sum(stage.values())
+    sw_gcups = cells_s / t_sw_s / 1e9
     return dict(value=cells / total / 1e9, unit="GCUPS", cores=cores, kind="oracle",
-                sample=f"MinHash (C) and LSH (numpy) on the first {ns} sequences; Smith-Waterman (C, "
-                       f"{cores} processes) on {Ps} of the oracle's candidate pairs of that subset, gate "
-                       f"fwd+bwd (numpy fp64) on {Pg} of them; each stage's time scaled linearly to the full "
-                       f"workload (sequences, DP cells, pairs)",
-                stage_s=dict(minhash=t_mh, lsh=t_lsh, align=t_sw, gate=t_gate),
-                sw_gcups=cells / t_sw / 1e9)
+                sample=f"MinHash (C) and LSH (numpy, one task per band) on all {n} sequences; Smith-Waterman "
+                       f"(C) on {Ps} and the gate fwd+bwd (numpy fp64) on {Pg} of the oracle's own "
+                       f"{P_oracle} candidate pairs (seeded sample), their times scaled linearly to the "
+                       f"full workload (DP cells, pairs); {cores} fork-pool processes, one thread each",
+                stage_s=stage, oracle_candidates=P_oracle,
+                rates={"minhash_seqs_per_s": n / stage["minhash"], "lsh_seqs_per_s": n / stage["lsh"],
+                       "sw_gcups": sw_gcups, "sw_gcups_1core": sw_1core,
+                       "gate_pairs_per_s": Pg / t_gate_s},
+                sw_gcups=sw_gcups)
 
 
 def bench_batch64(a, torch, sq):

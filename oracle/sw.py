@@ -72,20 +72,31 @@ def scores_pairs(seqs, lens, pairs, subst, gap_open=10, gap_extend=1) -> np.ndar
     return out
 
 
-def _pool_chunk(args):
-    seqs, lens, pairs, subst, go, ge = args
-    return scores_pairs(seqs, lens, pairs, subst, go, ge)
+_SHARED: dict = {}
+
+
+def _pool_chunk(k):
+    d = _SHARED
+    return scores_pairs(d["seqs"], d["lens"], d["chunks"][k], d["subst"], d["go"], d["ge"])
 
 
 def scores_pairs_parallel(seqs, lens, pairs, subst, gap_open=10, gap_extend=1, procs=None):
-    """Same as :func:`scores_pairs`, split over worker processes (CPU baseline timing)."""
+    """Same as :func:`scores_pairs`, split over worker processes (CPU baseline timing).
+
+    The tables reach the workers through the fork (module globals set before the pool
+    starts), so a task carries only its chunk index."""
     import multiprocessing as mp
     procs = procs or len(os.sched_getaffinity(0))
     pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
-    chunks = np.array_split(pairs, procs * 4)
     build()
-    with mp.get_context("fork").Pool(procs) as pool:
-        parts = pool.map(_pool_chunk, [(seqs, lens, c, subst, gap_open, gap_extend) for c in chunks])
+    _SHARED.update(seqs=np.ascontiguousarray(seqs, dtype=np.uint8), lens=np.ascontiguousarray(lens, dtype=np.int32),
+                   chunks=np.array_split(pairs, procs * 4), subst=np.ascontiguousarray(subst, dtype=np.int8),
+                   go=gap_open, ge=gap_extend)
+    try:
+        with mp.get_context("fork").Pool(procs) as pool:
+            parts = pool.map(_pool_chunk, range(len(_SHARED["chunks"])))
+    finally:
+        _SHARED.clear()
     return np.concatenate(parts) if parts else np.zeros(0, np.int32)
 
 
