@@ -161,8 +161,11 @@ int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int64_t n, int
  * so a gap of length k costs gap_open + (k - 1) * gap_extend.
  *   pairs [P][2] i32 (rows of seqs, any order, i == j allowed), scores [P] i32 (out).
  *   gap_open, gap_extend: positive costs, 0 <= gap_extend <= gap_open <= 1000.
- *   subst must be symmetric (as BLOSUM and PAM matrices are): each pair is aligned with its
- *   shorter sequence as the first operand.  Requires stride % 4 == 0, 4 <= stride <= 64.
+ *   subst [20][20] i8: subst[a][b] scores residue a of sequence i against residue b of
+ *   sequence j (a = pairs[p][0]'s residue); it need not be symmetric.  Each pair is aligned
+ *   with its shorter sequence down the register-resident rows; when that is sequence j the
+ *   transposed matrix is used (an asymmetric matrix costs a second pass over the pairs).
+ *   Requires stride % 4 == 0, 4 <= stride <= 64.
  */
 int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
                         const int32_t *pairs, int64_t P, const int8_t *subst,
@@ -261,7 +264,8 @@ int subquad_gate_train_set(const float *emb, int64_t n, int32_t d, const int32_t
  * global edit distance, on every pair:
  *   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost[a_x][b_y]),
  *   D[x][0] = x * indel, D[0][y] = y * indel; dist[p] = D[L_i][L_j] (i32).
- *   cost [20][20] i8 (device), symmetric, >= 0; 0 <= indel <= 1000.  The workspace is the
+ *   cost [20][20] i8 (device), >= 0, cost[a][b] for residue a of sequence i against b of
+ *   sequence j (need not be symmetric); 0 <= indel <= 1000.  The workspace is the
  *   alignment one (subquad_align_workspace_bytes(P)).  Requires stride % 4 == 0, <= 64.
  */
 int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,

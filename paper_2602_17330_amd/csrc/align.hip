@@ -244,48 +244,63 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
     if ((int64_t)blockIdx.x * (kAlignThreads / 64) >= ceil_div(hi - lo, 64)) return;  // whole block
     __shared__ uint32_t S2[kS2Words];
     __shared__ int8_t sub_sh[20 * 20];  // the 400 scores, loaded once (one load per thread)
-    for (int e = threadIdx.x; e < 20 * 20; e += blockDim.x) sub_sh[e] = subst[e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < kS2Words; e += blockDim.x) {
-        int c = e / (kCodes * kCodes);
-        int rem = e - c * (kCodes * kCodes);
-        int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
-        int s0, s1;
-        if (MODE == 0) {
-            s0 = a0 < 20 ? (int)sub_sh[a0 * 20 + c] : kMaskScore;
-            s1 = a1 < 20 ? (int)sub_sh[a1 * 20 + c] : kMaskScore;
-        } else {  // costs; rows past the end are never read back
-            s0 = a0 < 20 ? (int)sub_sh[a0 * 20 + c] : 0;
-            s1 = a1 < 20 ? (int)sub_sh[a1 * 20 + c] : 0;
-        }
-        S2[e] = ((uint32_t)(uint16_t)(int16_t)s0) | ((uint32_t)(uint16_t)(int16_t)s1 << 16);
+    int asym = 0;
+    for (int e = threadIdx.x; e < 20 * 20; e += blockDim.x) {
+        const int8_t v = subst[e], vt = subst[(e % 20) * 20 + e / 20];
+        sub_sh[e] = v;
+        asym |= v != vt;
     }
-    __syncthreads();
+    // A symmetric matrix (BLOSUM, PAM) needs one pass.  An asymmetric one takes a second pass
+    // over the block's pairs: the first aligns the pairs kept in (i, j) order, the second
+    // those whose operands were swapped (the longer i runs across the columns), with the
+    // table of the transposed matrix, since S(a_x, b_y) then reads S(col, row).
+    asym = __syncthreads_or(asym);
     const int lane = threadIdx.x & 63;
     const int64_t nw = ceil_div(hi - lo, 64);
     const int64_t wave0 = (int64_t)blockIdx.x * (kAlignThreads / 64) + (threadIdx.x >> 6);
     const int64_t wstep = (int64_t)gridDim.x * (kAlignThreads / 64);
-    for (int64_t wv = wave0; wv < nw; wv += wstep) {
-        const int64_t idx = lo + wv * 64 + lane;
-        bool valid = idx < hi;
-        int64_t p = 0;
-        if (valid) {
-            p = perm ? (int64_t)(uint32_t)perm[idx] : idx;
-            valid = p < P;
+    for (int pass = 0; pass <= asym; ++pass) {
+        if (pass) __syncthreads();  // every wave is done with the first pass's table
+        for (int e = threadIdx.x; e < kS2Words; e += blockDim.x) {
+            int c = e / (kCodes * kCodes);
+            int rem = e - c * (kCodes * kCodes);
+            int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
+            const int i0 = pass ? c * 20 + a0 : a0 * 20 + c, i1 = pass ? c * 20 + a1 : a1 * 20 + c;
+            int s0, s1;
+            if (MODE == 0) {
+                s0 = a0 < 20 ? (int)sub_sh[i0] : kMaskScore;
+                s1 = a1 < 20 ? (int)sub_sh[i1] : kMaskScore;
+            } else {  // costs; rows past the end are never read back
+                s0 = a0 < 20 ? (int)sub_sh[i0] : 0;
+                s1 = a1 < 20 ? (int)sub_sh[i1] : 0;
+            }
+            S2[e] = ((uint32_t)(uint16_t)(int16_t)s0) | ((uint32_t)(uint16_t)(int16_t)s1 << 16);
         }
-        if (valid && !pair_ok(pairs, n, p)) {
-            valid = false;
-            scores[p] = -1;
-        }
-        if (valid) {
-            int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
-            int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
-            const uint8_t *arow, *brow;
-            int la, lb;
-            if (li <= lj) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
-            else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
-            if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge, (stride >> 2) - 1);
-            else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, (stride >> 2) - 1);
+        __syncthreads();
+        for (int64_t wv = wave0; wv < nw; wv += wstep) {
+            const int64_t idx = lo + wv * 64 + lane;
+            bool valid = idx < hi;
+            int64_t p = 0;
+            if (valid) {
+                p = perm ? (int64_t)(uint32_t)perm[idx] : idx;
+                valid = p < P;
+            }
+            if (valid && !pair_ok(pairs, n, p)) {
+                valid = false;
+                if (pass == 0) scores[p] = -1;
+            }
+            if (valid) {
+                int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
+                int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
+                const bool swap = li > lj;
+                if (asym && swap != (pass == 1)) continue;
+                const uint8_t *arow, *brow;
+                int la, lb;
+                if (!swap) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
+                else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
+                if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge, (stride >> 2) - 1);
+                else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, (stride >> 2) - 1);
+            }
         }
     }
 }

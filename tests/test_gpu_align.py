@@ -5,7 +5,7 @@ import torch
 
 import paper_2602_17330_amd as sq
 import synth
-from helpers import dev, say, sw_oracle, workload
+from helpers import dev, oracle_candidates, oracle_scores, say, sw_oracle, workload
 from oracle import sw as osw
 
 pytestmark = pytest.mark.gpu
@@ -112,3 +112,59 @@ def test_rep1m_pairs_sampled(S):
     sel = synth.sample_rows(pairs.shape[0], 100_000, 2)
     assert np.array_equal(got[sel], sw_oracle(r.seqs, r.lens, pairs[sel], S))
     assert got.min() >= 0
+
+
+def test_rep1m_candidates_full(S):
+    """Every LSH candidate pair of the 1M-sequence workload (the pairs the benchmark aligns),
+    in the order the candidate stage emits them, against the C oracle score by score."""
+    r = workload("rep1m")
+    pairs = oracle_candidates("rep1m").astype(np.int32)
+    say(f"align rep1m candidates P={pairs.shape[0]}")
+    got = _gpu(r.seqs, r.lens, pairs, S)
+    say("align rep1m candidates: oracle scores")
+    assert np.array_equal(got, oracle_scores("rep1m"))
+
+
+def test_asymmetric_matrix(S):
+    """An asymmetric substitution matrix: subst[a][b] scores residue a of the pair's first
+    sequence against b of its second, whichever is shorter (the kernel's second pass over
+    pairs whose operands it swaps uses the transposed table).  Both orders of every pair, all
+    lengths 1-64, against the oracle."""
+    rng = np.random.default_rng(77)
+    A = np.clip(S.astype(np.int64) + rng.integers(-6, 7, (20, 20)), -30, 30).astype(np.int8)
+    assert not (A == A.T).all()
+    n, stride = 300, 64
+    lens = rng.integers(1, stride + 1, n).astype(np.int32)
+    seqs = np.full((n, stride), synth.PAD, np.uint8)
+    for i in range(n):
+        seqs[i, : lens[i]] = rng.integers(0, 20, lens[i])
+    pairs = np.stack([rng.integers(0, n, 4000), rng.integers(0, n, 4000)], 1).astype(np.int32)
+    pairs = np.concatenate([pairs, pairs[:, ::-1]]).astype(np.int32)
+    for go, ge in ((10, 1), (3, 2)):
+        say(f"align asymmetric matrix go={go} ge={ge}")
+        got = _gpu(seqs, lens, pairs, A, go, ge)
+        ref = sw_oracle(seqs, lens, pairs, A, go, ge)
+        assert np.array_equal(got, ref)
+        assert not np.array_equal(ref[:4000], ref[4000:])   # the orientation matters
+        assert np.array_equal(_gpu(seqs, lens, pairs, A, go, ge, nows=True), ref)
+
+
+def test_asymmetric_edit_costs():
+    """The edit-distance channel with an asymmetric cost matrix, both orders of every pair."""
+    from oracle import edit as oedit
+    rng = np.random.default_rng(78)
+    C = rng.integers(0, 5, (20, 20)).astype(np.int8)
+    np.fill_diagonal(C, 0)
+    n, stride = 200, 64
+    lens = rng.integers(1, stride + 1, n).astype(np.int32)
+    seqs = np.full((n, stride), synth.PAD, np.uint8)
+    for i in range(n):
+        seqs[i, : lens[i]] = rng.integers(0, 20, lens[i])
+    pairs = np.stack([rng.integers(0, n, 3000), rng.integers(0, n, 3000)], 1).astype(np.int32)
+    pairs = np.concatenate([pairs, pairs[:, ::-1]]).astype(np.int32)
+    say("edit distance asymmetric costs")
+    out = sq.edit_distance(dev(seqs), dev(lens), dev(pairs), dev(C), indel=3)
+    torch.cuda.synchronize()
+    ref = oedit.distances_pairs(seqs, lens, pairs, C, 3)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    assert not np.array_equal(ref[:3000], ref[3000:])

@@ -8,7 +8,8 @@ import torch
 
 import paper_2602_17330_amd as sq
 import synth
-from helpers import dev, fused_tol_ok, grad_tol_ok, say, sw_oracle, workload
+from helpers import (ambiguous_flip_bounds, dev, fused_tol_ok, gate_backward_chunked, grad_tol_ok, grads_ok_widened,
+                     oracle_candidates, oracle_scores, say, sw_oracle, workload)
 from oracle import gate as ogate
 from oracle import sw as osw
 
@@ -400,6 +401,86 @@ def test_gate_train_set_writes_demb(P, sorted_pairs):
     f2, l2, g2 = sq.api.gate_train(*args, lab, 0.5, grads=g2, set_demb=True)
     torch.cuda.synchronize()
     assert torch.equal(torch.nan_to_num(f1, nan=-7.0), torch.nan_to_num(f2, nan=-7.0))
+    assert l1.item() == l2.item()
+    assert not torch.isnan(g2[4]).any()
+    touched = np.zeros(n, bool)
+    ok = (c["pairs"] >= 0).all(axis=1) & (c["pairs"] < n).all(axis=1)
+    touched[c["pairs"][ok].ravel()] = True
+    assert not g2[4][torch.from_numpy(~touched).cuda()].any()
+    for a, b in zip(g1, g2):
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(a.abs().max()))
+
+
+def _rep1m_train_case(P, seed):
+    """P candidate pairs of the 1M-sequence workload (a seeded sample of the oracle's
+    candidate set, in its sorted order), their oracle alignment scores, d = 128, H = 64."""
+    rep = workload("rep1m")
+    cand = oracle_candidates("rep1m")
+    pick = np.sort(synth.sample_rows(cand.shape[0], P, seed))
+    S = synth.load_blosum62()
+    W1, b1, w2, b2 = synth.gate_params(64)
+    return rep, dict(emb=synth.embeddings(rep.seqs, rep.lens, 128), lens=rep.lens, vgene=rep.vgene,
+                     self_scores=osw.self_scores(rep.seqs, rep.lens, S),
+                     pairs=np.ascontiguousarray(cand[pick].astype(np.int32)),
+                     align=np.ascontiguousarray(oracle_scores("rep1m")[pick]), W1=W1, b1=b1, w2=w2, b2=b2)
+
+
+def test_gate_train_set_rep1m_2p20_against_oracle():
+    """The writing training pass the benchmark step runs, on 2^20 of the 1M workload's
+    candidate pairs (each 16-lane group walks tens of prefetched batches): fused values of
+    every pair, the mean loss, the weight gradients and every row of the embedding gradient
+    against the float64 oracle.  Hidden units within float32 rounding of the ReLU kink widen
+    the bounds by exactly what flipping each of them changes."""
+    rep, c = _rep1m_train_case(1 << 20, 1005)
+    lab = rep.family.astype(np.int32)
+    args = gpu_args(c)
+    W = args[6:]
+    g0 = tuple(torch.zeros_like(w) for w in W) + (torch.full_like(args[0], float("nan")),)
+    say(f"gate train set rep1m P={c['pairs'].shape[0]}")
+    fused, loss, grads = sq.api.gate_train(*args, dev(lab), 0.5, grads=g0, set_demb=True)
+    torch.cuda.synchronize()
+    fused = fused.cpu().numpy()
+    grads = [g.cpu().numpy() for g in grads]
+    say("gate train set rep1m: oracle forward")
+    oa = oracle_args(c)
+    f64 = ogate.forward(**oa)
+    ok, err = fused_tol_ok(fused, f64)
+    assert ok, err
+    y = (lab[c["pairs"][:, 0]] == lab[c["pairs"][:, 1]]).astype(np.float64)
+    L, gl = ogate.contrastive_loss(f64, y, 0.5)
+    assert abs(loss.item() - L) <= 1e-5 * abs(L) + 1e-7
+    say("gate train set rep1m: oracle backward")
+    ref = gate_backward_chunked(oa, gl)
+    n_amb, ew, nw = ambiguous_flip_bounds(oa, gl)
+    say(f"gate train set rep1m: {n_amb} ambiguous ReLU decisions")
+    assert not np.isnan(grads[4]).any()
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), grads):
+        ok, rel = grads_ok_widened(g, ref[name], ew[name], nw[name])
+        assert ok, (name, rel)
+
+
+@pytest.mark.parametrize("sorted_pairs", [True, False])
+def test_gate_train_set_rep1m_2p20_writes_demb(sorted_pairs):
+    """At 2^20 candidate pairs of the 1M workload, sorted and shuffled, with out-of-range
+    pairs mixed in: the writing pass on a NaN-filled gradient equals the accumulating pass on
+    zeros (rows without pairs zero, rows split between chunks complete)."""
+    rep, c = _rep1m_train_case(1 << 20, 1006)
+    n = rep.n
+    order = np.arange(c["pairs"].shape[0]) if sorted_pairs else np.random.default_rng(7).permutation(
+        c["pairs"].shape[0])
+    lone = int(np.setdiff1d(np.arange(n), c["pairs"][:, 0])[0])   # a row with no pair as i
+    bad = np.array([[n, 0], [2, n + 1], [lone, -1]], np.int32)
+    c = dict(c, pairs=np.ascontiguousarray(np.concatenate([c["pairs"][order], bad])),
+             align=np.ascontiguousarray(np.concatenate([c["align"][order], np.zeros(3, np.int32)])))
+    lab = dev(rep.family.astype(np.int32))
+    args = gpu_args(c)
+    say(f"gate train set vs accumulate rep1m P={c['pairs'].shape[0]} sorted={sorted_pairs}")
+    f1, l1, g1 = sq.api.gate_train(*args, lab, 0.5)
+    g2 = tuple(torch.zeros_like(g) for g in g1[:4]) + (torch.full_like(g1[4], float("nan")),)
+    f2, l2, g2 = sq.api.gate_train(*args, lab, 0.5, grads=g2, set_demb=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.nan_to_num(f1, nan=-7.0), torch.nan_to_num(f2, nan=-7.0))
+    assert np.isnan(f2[-3:].cpu().numpy()).all()
     assert l1.item() == l2.item()
     assert not torch.isnan(g2[4]).any()
     touched = np.zeros(n, bool)

@@ -6,7 +6,8 @@ import torch
 
 import paper_2602_17330_amd as sq
 import synth
-from helpers import dev, fused_tol_ok, grad_tol_ok, host_u64, say, sw_oracle, workload
+from helpers import (ambiguous_flip_bounds, dev, fused_tol_ok, gate_backward_chunked, grad_tol_ok, grads_ok_widened,
+                     host_u64, oracle_candidates, oracle_scores, oracle_sig, say, sw_oracle, workload)
 from oracle import gate as ogate
 from oracle import lsh as olsh
 from oracle import minhash as omh
@@ -204,3 +205,57 @@ def test_pipeline_step_against_oracle():
             ok_any = True
             break
     assert ok_any
+
+
+def test_pipeline_step_rep1m_against_oracle():
+    """The benchmark's own step (Pipeline.step on the 1M-sequence workload, M = 128, 32 x 4,
+    d = 128, H = 64, the fused gate pass with the embedding gradient written) against the
+    oracle chain at full size: every signature, the whole candidate set, every alignment
+    score, every fused value, the loss and every gradient element (bounds widened by the
+    ReLU decisions float32 may take either way)."""
+    from paper_2602_17330_amd.pipeline import PathConfig, Pipeline
+    rep = workload("rep1m")
+    S = synth.load_blosum62()
+    p = rep.params
+    emb = synth.embeddings(rep.seqs, rep.lens, p["d"])
+    W = synth.gate_params(64)
+    say("pipeline step rep1m")
+    pipe = Pipeline(rep.seqs, rep.lens, rep.vgene, rep.family, emb, S, *W,
+                    cfg=PathConfig(M=p["M"], b=p["b"], r=p["r"]), rep_offsets=rep.rep_offsets)
+    pipe.step()
+    pipe.step()                 # a second step over the same buffers (the benchmark repeats steps)
+    torch.cuda.synchronize()
+    P = pipe.P
+    got_sig = host_u64(pipe.sig)
+    got_pairs = pipe.pairs[:P].cpu().numpy().astype(np.int64)
+    got_scores = pipe.scores[:P].cpu().numpy()
+    got_fused = pipe.fused[:P].cpu().numpy()
+    got_loss = pipe.loss.item()
+    got = [g.cpu().numpy() for g in pipe.grads]
+    del pipe
+    torch.cuda.empty_cache()
+    say(f"pipeline step rep1m: P={P}; oracle signatures and candidates")
+    assert np.array_equal(got_sig, oracle_sig("rep1m"))
+    del got_sig
+    pairs = oracle_candidates("rep1m")
+    assert np.array_equal(got_pairs, pairs)
+    say("pipeline step rep1m: oracle alignment scores")
+    scores = oracle_scores("rep1m")
+    assert np.array_equal(got_scores, scores)
+    say("pipeline step rep1m: oracle gate forward")
+    oa = dict(emb=emb, lens=rep.lens, vgene=rep.vgene, self_scores=osw.self_scores(rep.seqs, rep.lens, S),
+              pairs=pairs, align=scores, W1=W[0], b1=W[1], w2=W[2], b2=W[3])
+    f64 = np.concatenate([ogate.forward(**dict(oa, pairs=pairs[lo:lo + (1 << 19)], align=scores[lo:lo + (1 << 19)]))
+                          for lo in range(0, P, 1 << 19)])
+    ok, err = fused_tol_ok(got_fused, f64)
+    assert ok, err
+    y = (rep.family[pairs[:, 0]] == rep.family[pairs[:, 1]]).astype(np.float64)
+    L, gl = ogate.contrastive_loss(f64, y, 0.5)
+    assert abs(got_loss - L) <= 1e-5 * abs(L)
+    say("pipeline step rep1m: oracle gate backward")
+    ref = gate_backward_chunked(oa, gl)
+    n_amb, ew, nw = ambiguous_flip_bounds(oa, gl)
+    say(f"pipeline step rep1m: {n_amb} ambiguous ReLU decisions")
+    for name, g in zip(("W1", "b1", "w2", "b2", "emb"), got):
+        ok, rel = grads_ok_widened(g, ref[name], ew[name], nw[name])
+        assert ok, (name, rel)

@@ -111,3 +111,23 @@ def test_m_gate_backward_autograd(mcase):
     assert np.allclose(got["f"], f.detach().numpy(), rtol=1e-13, atol=1e-15)
     for k in ("emb", "W1", "b1", "W2", "b2"):
         assert np.allclose(got[k], T[k].grad.numpy(), rtol=1e-11, atol=1e-13), k
+
+
+def test_bruteforce_asymmetric_costs():
+    """An asymmetric cost matrix: cost[a][b] for a residue of the first string against one of
+    the second; the C loop (both orders of a pair) equals the enumeration."""
+    rng = np.random.default_rng(4)
+    Ca = rng.integers(0, 5, (20, 20)).astype(np.int8)
+    np.fill_diagonal(Ca, 0)
+    differ = 0
+    for _ in range(40):
+        a = [int(x) % 5 for x in rng.integers(0, 20, rng.integers(1, 6))]
+        b = [int(x) % 5 for x in rng.integers(0, 20, rng.integers(1, 6))]
+        ref_ab, ref_ba = edit.distance_bruteforce(a, b, Ca, 3), edit.distance_bruteforce(b, a, Ca, 3)
+        seqs = np.full((2, 8), 0xFF, np.uint8)
+        seqs[0, : len(a)], seqs[1, : len(b)] = a, b
+        lens = np.array([len(a), len(b)], np.int32)
+        got = edit.distances_pairs(seqs, lens, np.array([[0, 1], [1, 0]], np.int32), Ca, 3)
+        assert list(got) == [ref_ab, ref_ba] and edit.distance_py(a, b, Ca, 3) == ref_ab
+        differ += ref_ab != ref_ba
+    assert differ > 0

@@ -35,6 +35,30 @@ def test_bruteforce_gappy_matrix():
         assert sw.score_c(a, b, S, 2, 1) == ref == sw.score_py(a, b, S, 2, 1)
 
 
+def test_bruteforce_asymmetric_matrix():
+    """An asymmetric matrix: subst[a][b] scores a residue of the first string against one of
+    the second.  The C loop (pairs entry, both orders) equals the enumeration, and the two
+    orders differ where the transposed matrix would give another score."""
+    rng = np.random.default_rng(3)
+    S = rng.integers(-6, 7, (20, 20)).astype(np.int8)
+    S[:4, :4] = [[5, 4, -2, -3], [-4, 6, 3, -1], [2, -5, 4, 1], [-2, 3, -3, 5]]
+    differ = 0
+    for k in range(30):
+        a, b = [x % 4 for x in _rand(rng, 2, 5)], [x % 4 for x in _rand(rng, 2, 4)]
+        go, ge = [(3, 1), (2, 1), (10, 1)][k % 3]
+        ref_ab = sw.score_bruteforce(a, b, S, go, ge)
+        ref_ba = sw.score_bruteforce(b, a, S, go, ge)
+        assert ref_ba == sw.score_bruteforce(a, b, S.T, go, ge)
+        assert sw.score_c(a, b, S, go, ge) == ref_ab == sw.score_py(a, b, S, go, ge)
+        seqs = np.full((2, 8), 0xFF, np.uint8)
+        seqs[0, : len(a)], seqs[1, : len(b)] = a, b
+        lens = np.array([len(a), len(b)], np.int32)
+        got = sw.scores_pairs(seqs, lens, np.array([[0, 1], [1, 0]], np.int32), S, go, ge)
+        assert list(got) == [ref_ab, ref_ba]
+        differ += ref_ab != ref_ba
+    assert differ > 0
+
+
 def _kadane_diagonals(a, b, S):
     best = 0
     for d in range(-len(a) + 1, len(b)):
