@@ -183,6 +183,26 @@ int subquad_align_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, 
                            size_t ws_bytes, void *stream);
 
 /*
+ * subquad_align_batch_noalloc -- for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * scores as subquad_align_batch, with the length sort's scratch taken from a fixed device
+ * array inside the library instead of an allocation.  No hipMalloc, hipFree or allocating
+ * call is made.
+ *   Arguments and results as subquad_align_batch.  P must be at most
+ *   SUBQUAD_ALIGN_NOALLOC_MAX_PAIRS, else SUBQUAD_ERR_ARG and nothing is enqueued.
+ *   The array (17 MiB) is held by every GPU the library runs on until the process ends.
+ *   All calls on one GPU share it: calls that overlap in time on one GPU (other streams,
+ *   other threads) race and give wrong scores; calls ordered on one stream are safe.
+ *   Nothing in the array needs to start at zero, so a call never reads what an earlier
+ *   call left there.
+ */
+#define SUBQUAD_ALIGN_NOALLOC_MAX_PAIRS (1 << 20)
+int subquad_align_batch_noalloc(const uint8_t *seqs, const int32_t *lens, int64_t n,
+                                int32_t stride, const int32_t *pairs, int64_t P,
+                                const int8_t *subst, int32_t gap_open, int32_t gap_extend,
+                                int32_t *scores, void *stream);
+
+/*
  * subquad_gate_fwd -- per-pair dynamic affinity fusion, Sec. 3.6, Eq. (wm) and (afused),
  * with the sigmoid channel weight of Eq. (alpha).  For pair p = (i, j):
  *   s = align[p] / sqrt(self[i] * self[j])      (alignment channel)

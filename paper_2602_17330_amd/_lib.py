@@ -35,6 +35,8 @@ SIGNATURES = {
     "subquad_align_workspace_bytes": (c_sz, [c_i64]),
     "subquad_align_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_i32,
                                               c_p, c_p, c_sz, c_p]),
+    "subquad_align_batch_noalloc": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_i32,
+                                                   c_p, c_p]),
     "subquad_gate_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p]),
     "subquad_gate_bwd_workspace_bytes": (c_sz, [c_i32, c_i64, c_i64]),

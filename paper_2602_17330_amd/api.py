@@ -141,6 +141,24 @@ def align(seqs: torch.Tensor, lens: torch.Tensor, pairs: torch.Tensor, subst: to
     return out
 
 
+def align_noalloc(seqs, lens, pairs, subst, gap_open=10, gap_extend=1, out=None) -> torch.Tensor:
+    """The allocation-free entry point (scratch in the library's fixed device array; at most
+    ALIGN_NOALLOC_MAX_PAIRS pairs)."""
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    subst = _dev(subst, torch.int8, "subst")
+    if out is None:
+        out = torch.empty(pairs.shape[0], dtype=torch.int32, device=seqs.device)
+    check(lib().subquad_align_batch_noalloc(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], _ptr(pairs),
+                                            pairs.shape[0], _ptr(subst), gap_open, gap_extend, _ptr(out),
+                                            _stream()))
+    return out
+
+
+ALIGN_NOALLOC_MAX_PAIRS = 1 << 20
+
+
 def align_nows(seqs, lens, pairs, subst, gap_open=10, gap_extend=1) -> torch.Tensor:
     """The entry point without a workspace (no length sort)."""
     seqs = _dev(seqs, torch.uint8, "seqs")

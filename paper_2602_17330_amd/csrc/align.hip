@@ -19,6 +19,9 @@
 // have the same unroll and nearly the same trip count.  Substitution scores come from an
 // LDS table that packs S(a_x, c) and S(a_x+1, c) for a row pair and a column residue c
 // into one 32-bit word (one ds_read per two cells).
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 #include "radix.h"
 
@@ -424,6 +427,53 @@ extern "C" int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int
     if (rc != SUBQUAD_OK) return rc;
     SQ_HIP(fe);
     return SUBQUAD_OK;
+}
+
+// Allocation-free variant: the length sort's scratch is a file-scope device array that each
+// GPU holds from the library's first use on it until the process ends.  In host code the
+// array's name is only a stand-in, so its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address reaches kernels.
+constexpr int64_t kNoAllocMaxPairs = SUBQUAD_ALIGN_NOALLOC_MAX_PAIRS;
+constexpr size_t kNoAllocScratchBytes = size_t(17) << 20;  // >= align_layout(kNoAllocMaxPairs).total
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static int noalloc_scratch(uint32_t **out) {
+    static std::mutex mu;
+    static std::vector<void *> ptrs;
+    int dev = 0;
+    SQ_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+    if (!ptrs[dev]) {
+        void *ptr = nullptr;
+        SQ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        SQ_REQUIRE(ptr != nullptr, SUBQUAD_ERR_HIP, "no device address for the alignment scratch array");
+        ptrs[dev] = ptr;
+    }
+    *out = static_cast<uint32_t *>(ptrs[dev]);
+    return SUBQUAD_OK;
+}
+
+extern "C" int subquad_align_batch_noalloc(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                           const int32_t *pairs, int64_t P, const int8_t *subst, int32_t gap_open,
+                                           int32_t gap_extend, int32_t *scores, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0 && P >= 0, SUBQUAD_ERR_ARG, "n and P must be >= 0");
+    SQ_REQUIRE(P <= kNoAllocMaxPairs, SUBQUAD_ERR_ARG,
+               "subquad_align_batch_noalloc takes at most %lld pairs (got %lld); use subquad_align_batch_ws",
+               (long long)kNoAllocMaxPairs, (long long)P);
+    SQ_REQUIRE(P == 0 || (seqs && lens && pairs && subst && scores), SUBQUAD_ERR_ARG, "null pointer argument");
+    SQ_REQUIRE(stride >= 4 && stride <= 64 && stride % 4 == 0, SUBQUAD_ERR_ARG,
+               "stride must be a multiple of 4 in 4..64 (got %d)", stride);
+    SQ_REQUIRE(gap_extend >= 0 && gap_open >= gap_extend && gap_open <= 1000, SUBQUAD_ERR_ARG,
+               "need 0 <= gap_extend <= gap_open <= 1000");
+    if (P == 0) return SUBQUAD_OK;
+    SQ_REQUIRE(align_layout(P).total <= kNoAllocScratchBytes, SUBQUAD_ERR_WORKSPACE,
+               "alignment scratch array too small for %lld pairs", (long long)P);
+    uint32_t *ws = nullptr;
+    const int rc = noalloc_scratch(&ws);
+    if (rc != SUBQUAD_OK) return rc;
+    return align_run(seqs, lens, n, stride, pairs, P, subst, gap_open, gap_extend, scores, ws, as_stream(stream));
 }
 
 extern "C" int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
