@@ -183,6 +183,19 @@ int subquad_align_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, 
                            size_t ws_bytes, void *stream);
 
 /*
+ * subquad_align_batch_dev -- subquad_align_batch_ws on a pair count that a producer left in
+ * device memory (the candidate count of subquad_lsh_candidates_async): no host
+ * synchronisation, so the call can be captured in a HIP graph and replayed on new inputs.
+ *   pairs [cap][2] i32; n_pairs_dev [1] i64 (device): the number of pairs P, read on the
+ *   device and clamped to [0, cap]; scores [cap] i32 (out; entries p >= P are not written).
+ *   ws / ws_bytes: at least subquad_align_workspace_bytes(cap) bytes.
+ */
+int subquad_align_batch_dev(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                            const int32_t *pairs, int64_t cap, const int64_t *n_pairs_dev,
+                            const int8_t *subst, int32_t gap_open, int32_t gap_extend,
+                            int32_t *scores, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * subquad_align_batch_noalloc -- for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * scores as subquad_align_batch, with the length sort's scratch taken from a fixed device
@@ -278,6 +291,25 @@ int subquad_gate_train_set(const float *emb, int64_t n, int32_t d, const int32_t
                            float margin, float *fused, double *loss, float *dW1, float *db1,
                            float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes,
                            void *stream);
+
+/*
+ * subquad_gate_train_set_dev -- subquad_gate_train_set on a pair count that a producer
+ * left in device memory (the candidate count of subquad_lsh_candidates_async), so that the
+ * candidate, alignment and gate stages run with no host synchronisation and can be
+ * captured once in a HIP graph and replayed on new inputs (Eq. (batch): a batch sized
+ * against device memory, processed with launches sized for its capacity).
+ *   cap: the capacity the launches and the workspace are sized for (pairs has cap rows);
+ *   n_pairs_dev [1] i64 (device): the number of pairs P, read on the device and clamped to
+ *   [0, cap].  Entries p >= P of fused are not written.  Otherwise as
+ *   subquad_gate_train_set, with ws of subquad_gate_bwd_workspace_bytes(H, cap, n) bytes.
+ */
+int subquad_gate_train_set_dev(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                               const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                               const int32_t *align, int64_t cap, const int64_t *n_pairs_dev,
+                               const float *W1, const float *b1, const float *w2, const float *b2,
+                               int32_t H, const int32_t *label, float margin, float *fused,
+                               double *loss, float *dW1, float *db1, float *dw2, float *db2,
+                               float *demb, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * subquad_edit_batch_ws -- the paper's own affinity recurrence (Appendix F.3), a weighted

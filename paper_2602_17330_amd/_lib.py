@@ -35,6 +35,8 @@ SIGNATURES = {
     "subquad_align_workspace_bytes": (c_sz, [c_i64]),
     "subquad_align_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_i32,
                                               c_p, c_p, c_sz, c_p]),
+    "subquad_align_batch_dev": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_p, c_i32, c_i32,
+                                               c_p, c_p, c_sz, c_p]),
     "subquad_align_batch_noalloc": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_i32,
                                                    c_p, c_p]),
     "subquad_gate_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
@@ -45,6 +47,9 @@ SIGNATURES = {
     "subquad_gate_train_set": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p, c_p,
                                               c_i32, c_p, ctypes.c_float, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz,
                                               c_p]),
+    "subquad_gate_train_set_dev": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_p,
+                                                  c_p, c_p, c_i32, c_p, ctypes.c_float, c_p, c_p, c_p, c_p, c_p, c_p,
+                                                  c_p, c_p, c_sz, c_p]),
     "subquad_gate_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
     "subquad_edit_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p, c_sz,

@@ -141,6 +141,26 @@ def align(seqs: torch.Tensor, lens: torch.Tensor, pairs: torch.Tensor, subst: to
     return out
 
 
+def align_dev(seqs, lens, pairs, subst, n_pairs_dev, gap_open=10, gap_extend=1, out=None, ws=None) -> torch.Tensor:
+    """Scores of the first ``*n_pairs_dev`` rows of ``pairs`` (a device count; ``pairs`` has the
+    capacity's rows).  No host synchronisation."""
+    seqs = _dev(seqs, torch.uint8, "seqs")
+    lens = _dev(lens, torch.int32, "lens")
+    pairs = _dev(pairs, torch.int32, "pairs")
+    subst = _dev(subst, torch.int8, "subst")
+    n_pairs_dev = _dev(n_pairs_dev, torch.int64, "n_pairs_dev")
+    cap = pairs.shape[0]
+    if out is None:
+        out = torch.empty(cap, dtype=torch.int32, device=seqs.device)
+    need = align_workspace_bytes(cap)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=seqs.device)
+    check(lib().subquad_align_batch_dev(_ptr(seqs), _ptr(lens), seqs.shape[0], seqs.shape[1], _ptr(pairs), cap,
+                                        _ptr(n_pairs_dev), _ptr(subst), gap_open, gap_extend, _ptr(out), _ptr(ws),
+                                        ws.numel(), _stream()))
+    return out
+
+
 def align_noalloc(seqs, lens, pairs, subst, gap_open=10, gap_extend=1, out=None) -> torch.Tensor:
     """The allocation-free entry point (scratch in the library's fixed device array; at most
     ALIGN_NOALLOC_MAX_PAIRS pairs)."""
@@ -248,6 +268,30 @@ def gate_train(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, labels,
     check(fn(_ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s), _ptr(pairs),
              _ptr(align_s), P, _ptr(W1), _ptr(b1), _ptr(w2), _ptr(b2), H, _ptr(labels), margin, _ptr(fused),
              _ptr(loss), *[_ptr(g) for g in grads], _ptr(ws), ws.numel(), _stream()))
+    return fused, loss, grads
+
+
+def gate_train_set_dev(emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2, labels, n_pairs_dev,
+                       margin: float = 0.5, fused=None, loss=None, grads=None, ws: torch.Tensor | None = None):
+    """``gate_train`` with the embedding gradient written, on the first ``*n_pairs_dev`` rows of
+    ``pairs`` (a device count; ``pairs`` has the capacity's rows).  No host synchronisation."""
+    emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2 = _gate_args(
+        emb, lens, vgene, self_s, pairs, align_s, W1, b1, w2, b2)
+    labels = _dev(labels, torch.int32, "labels")
+    n_pairs_dev = _dev(n_pairs_dev, torch.int64, "n_pairs_dev")
+    H, cap = W1.shape[0], pairs.shape[0]
+    fused = torch.empty(cap, dtype=torch.float32, device=emb.device) if fused is None else fused
+    loss = torch.empty(1, dtype=torch.float64, device=emb.device) if loss is None else loss
+    if grads is None:
+        grads = (torch.zeros_like(W1), torch.zeros_like(b1), torch.zeros_like(w2), torch.zeros_like(b2),
+                 torch.empty_like(emb))
+    need = gate_bwd_workspace_bytes(H, cap, emb.shape[0])
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=emb.device)
+    check(lib().subquad_gate_train_set_dev(
+        _ptr(emb), emb.shape[0], emb.shape[1], _ptr(lens), _ptr(vgene), _ptr(self_s), _ptr(pairs), _ptr(align_s),
+        cap, _ptr(n_pairs_dev), _ptr(W1), _ptr(b1), _ptr(w2), _ptr(b2), H, _ptr(labels), margin, _ptr(fused),
+        _ptr(loss), *[_ptr(g) for g in grads], _ptr(ws), ws.numel(), _stream()))
     return fused, loss, grads
 
 

@@ -1,4 +1,5 @@
-"""Memory-sized batching of repertoires (Sec. 3.5, Eq. (batch)).
+"""Memory-sized batching of repertoires (Eq. (batch), "Data normalization and hardware-aware
+batching").
 
 The paper sizes a batch as B = min(|S|, max(32, floor(sqrt(M_avail / (c * l_max))))): the
 square root belongs to an all-pairs B x B comparison tile.  Behind the MinHash prefilter the
@@ -22,9 +23,12 @@ def bytes_per_sequence(M: int, b: int, d: int, stride: int, pairs_per_seq: float
     per_seq = (stride + 4 + 4 + 4 + 4          # sequence row, length, V-gene, family, self-score
                + 8 * M                          # signature row
                + 2 * 8 * b + b                  # band records (two sort buffers) + fingerprints
-               + 8 + 8                          # CSR row offset, length-sort slot
+               + 8 + 16                         # CSR row offset, gate node record
                + 2 * 4 * d)                     # embedding and its gradient
-    per_pair = 8 + 2 * 8 + 4 + 4 + 4 + 4        # pair, pair-sort keys (x2), score, fused, grad, perm
+    per_pair = (8 + 2 * 8                        # pair, pair-sort keys (x2)
+                + 4 + 4 + 4                      # score, fused, upstream gradient
+                + 2 * 8                          # alignment length sort (x2)
+                + 4 * 8 + 16 + 16)               # gate pair orders (x4), per-pair records (2 x 16)
     return per_seq + pairs_per_seq * per_pair
 
 

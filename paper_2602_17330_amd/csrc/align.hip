@@ -62,9 +62,18 @@ __device__ __forceinline__ int align_key(int lmin, int lmax) {
     return (rb - 1) * 64 + (max(lmax, 1) - 1);
 }
 
+// Pairs to process: cap, or min(*count_dev, cap) when a producer left the count on the device.
+__device__ __forceinline__ int64_t align_count(int64_t cap, const int64_t *__restrict__ count_dev) {
+    if (!count_dev) return cap;
+    const int64_t c = *count_dev;
+    return c < 0 ? 0 : (c < cap ? c : cap);
+}
+
 __global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restrict__ pairs,
-                                                         const int32_t *__restrict__ lens, int64_t n, int64_t P,
+                                                         const int32_t *__restrict__ lens, int64_t n, int64_t cap,
+                                                         const int64_t *__restrict__ P_dev,
                                                          uint64_t *__restrict__ rec) {
+    const int64_t P = align_count(cap, P_dev);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         int lmin = 1, lmax = 1;
         if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
@@ -73,8 +82,10 @@ __global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restri
 }
 
 // bin_end[k] = number of sorted records with key <= k (one thread per key, binary search).
-__global__ __launch_bounds__(kAlignKeyBins) void align_bins_kernel(const uint64_t *__restrict__ srec, int64_t P,
+__global__ __launch_bounds__(kAlignKeyBins) void align_bins_kernel(const uint64_t *__restrict__ srec, int64_t cap,
+                                                                   const int64_t *__restrict__ P_dev,
                                                                    uint32_t *__restrict__ bin_end) {
+    const int64_t P = align_count(cap, P_dev);
     const uint64_t k = threadIdx.x;
     int64_t lo = 0, hi = P;
     while (lo < hi) {
@@ -343,9 +354,11 @@ extern "C" int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int
 
 // The length sort needs P + 512 words of scratch; it is taken from a stream-ordered
 // allocation only when the caller passes no workspace (the plain entry point below).
+// P is the number of pairs, or with P_dev the capacity and *P_dev (read on the device) the
+// number.
 static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, const int32_t *pairs, int64_t P,
                      const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st,
-                     int mode = 0) {
+                     int mode = 0, const int64_t *P_dev = nullptr) {
     // Length sort: records (bucket key << 32 | p) sorted on their 9 key bits by the stable
     // radix sort; then bin_end[k] = first position whose key exceeds k.
     char *base = reinterpret_cast<char *>(scratch);
@@ -354,12 +367,12 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     uint64_t *rb = reinterpret_cast<uint64_t *>(base + L.rb);
     uint32_t *hist = reinterpret_cast<uint32_t *>(base + L.bins);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
-    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, ra);
+    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, P_dev, ra);
     SQ_LAUNCHED("align_keys_kernel");
     uint64_t *sorted = nullptr;
-    int rc = radix_sort_u64(ra, rb, P, nullptr, 32, 9, base + L.radix, L.total - L.radix, st, &sorted, "sort_lengths");
+    int rc = radix_sort_u64(ra, rb, P, P_dev, 32, 9, base + L.radix, L.total - L.radix, st, &sorted, "sort_lengths");
     if (rc != SUBQUAD_OK) return rc;
-    align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, hist);
+    align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, P_dev, hist);
     SQ_LAUNCHED("align_bins_kernel");
     uint64_t *perm = sorted;  // the pair index is the low word of each sorted record
     const int64_t waves = ceil_div(P, 64);
@@ -427,6 +440,26 @@ extern "C" int subquad_align_batch(const uint8_t *seqs, const int32_t *lens, int
     if (rc != SUBQUAD_OK) return rc;
     SQ_HIP(fe);
     return SUBQUAD_OK;
+}
+
+extern "C" int subquad_align_batch_dev(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
+                                       const int32_t *pairs, int64_t cap, const int64_t *n_pairs_dev,
+                                       const int8_t *subst, int32_t gap_open, int32_t gap_extend, int32_t *scores,
+                                       void *ws, size_t ws_bytes, void *stream) {
+    clear_error();
+    SQ_REQUIRE(n >= 0 && cap >= 0, SUBQUAD_ERR_ARG, "n and cap must be >= 0");
+    SQ_REQUIRE(cap == 0 || (seqs && lens && pairs && subst && scores && n_pairs_dev), SUBQUAD_ERR_ARG,
+               "null pointer argument");
+    SQ_REQUIRE(stride >= 4 && stride <= 64 && stride % 4 == 0, SUBQUAD_ERR_ARG,
+               "stride must be a multiple of 4 in 4..64 (got %d)", stride);
+    SQ_REQUIRE(gap_extend >= 0 && gap_open >= gap_extend && gap_open <= 1000, SUBQUAD_ERR_ARG,
+               "need 0 <= gap_extend <= gap_open <= 1000");
+    SQ_REQUIRE(cap < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "cap must be below 2^32");
+    if (cap == 0) return SUBQUAD_OK;
+    SQ_REQUIRE(ws && ws_bytes >= subquad_align_workspace_bytes(cap), SUBQUAD_ERR_WORKSPACE,
+               "alignment workspace too small");
+    return align_run(seqs, lens, n, stride, pairs, cap, subst, gap_open, gap_extend, scores, static_cast<uint32_t *>(ws),
+                     as_stream(stream), 0, n_pairs_dev);
 }
 
 // Allocation-free variant: the length sort's scratch is a file-scope device array that each

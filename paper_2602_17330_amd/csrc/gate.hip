@@ -36,7 +36,12 @@ struct GateIn {
     // (self score, length, V-gene, label) per node, one 16-byte record: a partner costs one
     // gather instead of four.  NULL: the separate arrays above are read.
     const int4 *node;
+    // When set, the number of pairs is min(*P_dev, P) read on the device (P is then the
+    // capacity the launches are sized for).
+    const int64_t *P_dev;
 };
+
+__device__ __forceinline__ int64_t live_pairs(const GateIn &in) { return live_count(in.P, in.P_dev); }
 
 // node[k] = (self[k], lens[k], vgene[k], label ? label[k] : 0).
 __global__ void gate_node_pack_kernel(const int32_t *__restrict__ self, const int32_t *__restrict__ lens,
@@ -199,8 +204,9 @@ __global__ __launch_bounds__(kGateThreads) void gate_fwd_kernel(GateIn in, float
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(in.P, ngroups);
-    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    const int64_t P = live_pairs(in);
+    const int64_t chunk = ceil_div(P, ngroups);
+    const int64_t p0 = group * chunk, p1 = min(P, p0 + chunk);
     __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
     stage_weights(in, wsh);
     if (p0 >= p1) return;
@@ -268,7 +274,7 @@ template <int NV, int UNITS, bool TRAIN, bool NATURAL>
 __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *__restrict__ gfused,
                                                 const uint64_t *__restrict__ order_i, const float *wsh,
                                                 float4 *__restrict__ pack, float4 *__restrict__ feat,
-                                                float *__restrict__ demb, const TrainOut &tr, int64_t q0,
+                                                float *__restrict__ demb, const TrainOut &tr, int64_t P, int64_t q0,
                                                 int64_t q1, int l, int d4, float b2, float4 (*stage)[2],
                                                 float *fstage) {
     double loss_acc = 0.0;
@@ -411,7 +417,7 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
         }
     }
     if (cur_i >= 0 && demb) {
-        const bool ends_here = q1 == in.P || (int64_t)(order_i[q1] >> 32) != cur_i;
+        const bool ends_here = q1 == P || (int64_t)(order_i[q1] >> 32) != cur_i;
         flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here && ends_here);
     }
     return loss_acc;
@@ -427,11 +433,13 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     // Pairs already in order of i (the candidate lists are): walk them as they are, p = q.
     const bool natural = unsorted[0] == 0;
     const uint64_t *__restrict__ order_i = natural ? order_nat : order_sorted;
+    const int64_t P = live_pairs(in);
+    if (in.P_dev) tr.inv_P = 1.f / (float)(P > 0 ? P : 1);  // (the host forms it when P is known there)
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(in.P, ngroups);
-    const int64_t q0 = group * chunk, q1 = min(in.P, q0 + chunk);
+    const int64_t chunk = ceil_div(P, ngroups);
+    const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
     const int d4 = in.d >> 2;
     __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
     stage_weights(in, wsh);
@@ -441,9 +449,9 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ float fstage[kGateThreads / kGroup][kGateBatch];
     const int g = threadIdx.x / kGroup;
     const double loss_acc =
-        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat, demb, tr, q0, q1, l, d4,
+        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1, l, d4,
                                                         b2, stage[g], fstage[g])
-                : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat, demb, tr, q0, q1, l,
+                : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1, l,
                                                          d4, b2, stage[g], fstage[g]);
     if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
         __shared__ double red[kGateThreads];
@@ -471,11 +479,12 @@ template <int UNITS>
 __global__ __launch_bounds__(kGateThreads) void gate_wgrad_kernel(GateIn in, const float4 *__restrict__ pack,
                                                                   const float4 *__restrict__ feat,
                                                                   double *__restrict__ wpart) {
+    const int64_t P = live_pairs(in);
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(in.P, ngroups);
-    const int64_t p0 = group * chunk, p1 = min(in.P, p0 + chunk);
+    const int64_t chunk = ceil_div(P, ngroups);
+    const int64_t p0 = group * chunk, p1 = min(P, p0 + chunk);
     float W1[UNITS][4], b1[UNITS], w2[UNITS], b2;
     load_weights<UNITS>(in, l, W1, b1, w2, b2);
     double aW1[UNITS][4], ab1[UNITS], aw2[UNITS], ab2 = 0.0;
@@ -659,10 +668,12 @@ __global__ void fill_f32_kernel(float *__restrict__ x, int64_t count, float v) {
 // contiguous stores.
 __global__ __launch_bounds__(256) void gate_set_rows_prep_kernel(const uint64_t *__restrict__ order_nat,
                                                                  const uint64_t *__restrict__ order_sorted,
-                                                                 const int64_t *__restrict__ unsorted, int64_t P,
-                                                                 int64_t n, int64_t chunk, int d4,
-                                                                 float *__restrict__ demb) {
+                                                                 const int64_t *__restrict__ unsorted, int64_t cap,
+                                                                 const int64_t *__restrict__ P_dev, int64_t n,
+                                                                 int64_t ngroups, int d4, float *__restrict__ demb) {
     const uint64_t *order_i = unsorted[0] == 0 ? order_nat : order_sorted;
+    const int64_t P = live_count(cap, P_dev);
+    const int64_t chunk = ceil_div(P, ngroups);  // the first pass's chunk of pairs per lane group
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -706,10 +717,11 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
             const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U, TRAIN>);                 \
             if (lblocks) *lblocks = blocks;                                                                        \
             if (demb && tr.set_demb) {                                                                             \
-                const int64_t chunk = ceil_div(in.P, blocks * (kGateThreads / kGroup));                           \
                 const int64_t pblocks = std::min<int64_t>(ceil_div(in.P + 1, 256), gate_max_blocks() * 4);          \
                 gate_set_rows_prep_kernel<<<(unsigned)pblocks, 256, 0, st>>>(o.order_nat, o.order_i, o.unsorted, in.P, \
-                                                                             in.n, chunk, in.d >> 2, demb);        \
+                                                                             in.P_dev, in.n,                       \
+                                                                             blocks * (kGateThreads / kGroup),    \
+                                                                             in.d >> 2, demb);                     \
                 SQ_LAUNCHED("gate_set_rows_prep_kernel");                                                          \
             }                                                                                                      \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
@@ -737,8 +749,8 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
     if (demb) {
         const int64_t blocks = gate_blocks(in.P, (const void *)gate_cos_bwd_j_kernel<NV>);
         ProfScope prof("gate_cos_bwd_j_kernel", st);
-        gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, order_j,
-                                                                             pack, demb);
+        gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, in.P_dev,
+                                                                             order_j, pack, demb);
     }
     SQ_LAUNCHED("gate_cos_bwd_j_kernel");
     return SUBQUAD_OK;
@@ -775,8 +787,9 @@ __global__ void gate_sorted_init_kernel(int64_t *__restrict__ flags) {
     if (threadIdx.x == 0 && blockIdx.x == 0) flags[0] = 0;
 }
 
-__global__ void gate_sorted_check_kernel(const int32_t *__restrict__ pairs, int64_t P, int64_t n,
-                                         int64_t *__restrict__ flags) {
+__global__ void gate_sorted_check_kernel(const int32_t *__restrict__ pairs, int64_t cap,
+                                         const int64_t *__restrict__ P_dev, int64_t n, int64_t *__restrict__ flags) {
+    const int64_t P = live_count(cap, P_dev);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p + 1 < P; p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t a = pairs[2 * p], b = pairs[2 * p + 2];
         const int64_t ka = (a < 0 || a >= n || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= n) ? n : a;
@@ -786,16 +799,16 @@ __global__ void gate_sorted_check_kernel(const int32_t *__restrict__ pairs, int6
 }
 
 // flags[1] = records the sort by i takes: P when the pairs are out of order, else none.
-__global__ void gate_sorted_count_kernel(int64_t *__restrict__ flags, int64_t P) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) flags[1] = flags[0] ? P : 0;
+__global__ void gate_sorted_count_kernel(int64_t *__restrict__ flags, int64_t cap, const int64_t *__restrict__ P_dev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) flags[1] = flags[0] ? live_count(cap, P_dev) : 0;
 }
 
 // Orders of the pair indices by their first and by their second index (stable, so each row
 // keeps the input order) for the two backward passes.  When the pairs already come in order
 // of i (the candidate lists do), the i sort is given no records and the first pass walks the
 // pairs as they are.
-static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws, const GateBwdLayout &L,
-                            hipStream_t st, GateOrders &o) {
+static int gate_pair_orders(const int32_t *pairs, int64_t P, const int64_t *P_dev, int64_t n, char *ws,
+                            const GateBwdLayout &L, hipStream_t st, GateOrders &o) {
     uint64_t *ra = reinterpret_cast<uint64_t *>(ws + L.ra), *rb = reinterpret_cast<uint64_t *>(ws + L.rb);
     uint64_t *rc = reinterpret_cast<uint64_t *>(ws + L.rc), *rd = reinterpret_cast<uint64_t *>(ws + L.rd);
     int64_t *flags = reinterpret_cast<int64_t *>(ws + L.flags);
@@ -803,11 +816,11 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws
     const int bits = key_bits_for(n);
     gate_sorted_init_kernel<<<1, 64, 0, st>>>(flags);
     SQ_LAUNCHED("gate_sorted_init_kernel");
-    gate_sorted_check_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, flags);
+    gate_sorted_check_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, P_dev, n, flags);
     SQ_LAUNCHED("gate_sorted_check_kernel");
-    gate_sorted_count_kernel<<<1, 64, 0, st>>>(flags, P);
+    gate_sorted_count_kernel<<<1, 64, 0, st>>>(flags, P, P_dev);
     SQ_LAUNCHED("gate_sorted_count_kernel");
-    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 0, ra);
+    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, P_dev, n, 0, ra);
     SQ_LAUNCHED("gate_order_keys_kernel");
     // With no records to sort (pairs already in order) the sort writes nothing and ra keeps
     // the natural order, which is then the one used; otherwise its result is.
@@ -815,9 +828,9 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, int64_t n, char *ws
     int rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, L.total - L.radix, st, &order_i,
                              "sort_gate_i");
     if (rc_ != SUBQUAD_OK) return rc_;
-    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, n, 1, rc);
+    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, P_dev, n, 1, rc);
     SQ_LAUNCHED("gate_order_keys_kernel");
-    rc_ = radix_sort_u64(rc, rd, P, nullptr, 32, bits, ws + L.radix, L.total - L.radix, st, &order_j, "sort_gate_j");
+    rc_ = radix_sort_u64(rc, rd, P, P_dev, 32, bits, ws + L.radix, L.total - L.radix, st, &order_j, "sort_gate_j");
     if (rc_ != SUBQUAD_OK) return rc_;
     o = GateOrders{ra, order_i, order_j, flags};
     return SUBQUAD_OK;
@@ -866,7 +879,9 @@ __global__ __launch_bounds__(kLossThreads) void contrastive_kernel(const float *
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void contrastive_final_kernel(const double *__restrict__ partial, int nb, int64_t P, double *__restrict__ loss) {
+__global__ void contrastive_final_kernel(const double *__restrict__ partial, int nb, int64_t cap,
+                                         const int64_t *__restrict__ P_dev, double *__restrict__ loss) {
+    const int64_t P = live_count(cap, P_dev);
     __shared__ double red[kLossThreads];
     double a = 0.0;
     for (int k = threadIdx.x; k < nb; k += kLossThreads) a += partial[k];
@@ -936,7 +951,7 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
     double *lpart = reinterpret_cast<double *>(w + L.lpart);
     if (in.P == 0) {
         if (TRAIN) {
-            contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, 0, 0, loss);
+            contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, 0, 0, nullptr, loss);
             SQ_LAUNCHED("contrastive_final_kernel");
         }
         if (set_demb && demb && in.n > 0) {  // no pairs: the written gradient is zero
@@ -955,7 +970,7 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
     }
     in.node = node;
     GateOrders orders{};
-    rc = gate_pair_orders(in.pairs, in.P, in.n, w, L, st, orders);
+    rc = gate_pair_orders(in.pairs, in.P, in.P_dev, in.n, w, L, st, orders);
     if (rc != SUBQUAD_OK) return rc;
     float4 *pack = reinterpret_cast<float4 *>(w + L.pack);
     float4 *feat = reinterpret_cast<float4 *>(w + L.feat);
@@ -974,7 +989,7 @@ static int gate_backward(const GateIn &in0, const int32_t *label, const float *g
                                                db2, st);
     if (rc != SUBQUAD_OK) return rc;
     if (TRAIN) {
-        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, (int)lblocks, in.P, loss);
+        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(lpart, (int)lblocks, in.P, in.P_dev, loss);
         SQ_LAUNCHED("contrastive_final_kernel");
     }
     return SUBQUAD_OK;
@@ -1014,6 +1029,20 @@ extern "C" int subquad_gate_train_set(const float *emb, int64_t n, int32_t d, co
                                true);
 }
 
+extern "C" int subquad_gate_train_set_dev(const float *emb, int64_t n, int32_t d, const int32_t *lens,
+                                          const int32_t *vgene, const int32_t *self, const int32_t *pairs,
+                                          const int32_t *align, int64_t cap, const int64_t *n_pairs_dev,
+                                          const float *W1, const float *b1, const float *w2, const float *b2, int32_t H,
+                                          const int32_t *label, float margin, float *fused, double *loss, float *dW1,
+                                          float *db1, float *dw2, float *db2, float *demb, void *ws, size_t ws_bytes,
+                                          void *stream) {
+    clear_error();
+    SQ_REQUIRE(n_pairs_dev, SUBQUAD_ERR_ARG, "null n_pairs_dev");
+    const GateIn in{emb, n, d, lens, vgene, self, pairs, align, cap, W1, b1, w2, b2, H, nullptr, n_pairs_dev};
+    return gate_backward<true>(in, label, nullptr, margin, fused, loss, dW1, db1, dw2, db2, demb, ws, ws_bytes, stream,
+                               true);
+}
+
 extern "C" size_t subquad_contrastive_workspace_bytes(void) { return sizeof(double) * (size_t)contrastive_blocks(); }
 
 extern "C" int subquad_contrastive_grad(const float *fused, const int32_t *pairs, int64_t P, const int32_t *label,
@@ -1033,7 +1062,7 @@ extern "C" int subquad_contrastive_grad(const float *fused, const int32_t *pairs
     contrastive_kernel<<<(unsigned)nb, kLossThreads, 0, st>>>(fused, pairs, P, label, n, margin, grad, partial);
     SQ_LAUNCHED("contrastive_kernel");
     if (loss) {
-        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(partial, nb, P, loss);
+        contrastive_final_kernel<<<1, kLossThreads, 0, st>>>(partial, nb, P, nullptr, loss);
         SQ_LAUNCHED("contrastive_final_kernel");
     }
     return SUBQUAD_OK;

@@ -38,6 +38,15 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// Pairs to process: `cap`, or the count a producer left in device memory (clamped to
+// [0, cap]) when `count_dev` is set, so that a launch sized for the capacity needs no host
+// synchronisation.
+__device__ __forceinline__ int64_t live_count(int64_t cap, const int64_t *__restrict__ count_dev) {
+    if (!count_dev) return cap;
+    const int64_t c = *count_dev;
+    return c < 0 ? 0 : (c < cap ? c : cap);
+}
+
 template <int NV>
 __device__ __forceinline__ void load_row(const float *__restrict__ emb, int64_t row, int d4, int l, float4 (&v)[NV]) {
     const float4 *r = reinterpret_cast<const float4 *>(emb) + row * d4;
@@ -138,9 +147,11 @@ __device__ __forceinline__ void flush_row_pre(float *__restrict__ demb, int64_t 
 template <int NV>
 __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const float *__restrict__ emb, int64_t n,
                                                                       int32_t d, const int32_t *__restrict__ pairs,
-                                                                      int64_t P, const uint64_t *__restrict__ order_j,
+                                                                      int64_t cap, const int64_t *__restrict__ P_dev,
+                                                                      const uint64_t *__restrict__ order_j,
                                                                       const float4 *__restrict__ pack,
                                                                       float *__restrict__ demb) {
+    const int64_t P = live_count(cap, P_dev);
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
@@ -232,8 +243,10 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
 // with either index out of range (such pairs sort last on both sides; the same key as the
 // in-order check of the pairs gives them, so that a natural order passed by that check is
 // in order of these keys too).
-static __global__ void gate_order_keys_kernel(const int32_t *__restrict__ pairs, int64_t P, int64_t n, int side,
-                                       uint64_t *__restrict__ rec) {
+static __global__ void gate_order_keys_kernel(const int32_t *__restrict__ pairs, int64_t cap,
+                                              const int64_t *__restrict__ P_dev, int64_t n, int side,
+                                              uint64_t *__restrict__ rec) {
+    const int64_t P = live_count(cap, P_dev);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         const int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
         const bool ok = i >= 0 && i < n && j >= 0 && j < n;

@@ -140,6 +140,68 @@ def test_graph_replay_matches_eager():
         del junk
 
 
+def test_graph_replays_on_a_new_batch():
+    """One captured step replayed on new inputs of the same shape (other sequences, other
+    repertoire boundaries, another candidate count): the replay equals an eager step on
+    those inputs with the same capacity and the oracle; a batch whose candidates overflow
+    the capacity is reported by the status, not run past it."""
+    from paper_2602_17330_amd.pipeline import PathConfig, Pipeline
+    S = synth.load_blosum62()
+    W = synth.gate_params(64)
+    cfg = PathConfig(M=64, b=16, r=4)
+
+    def batch(parts):
+        rep = synth.concat([synth.tiny(n_families=f, fam_size=m, seed=sd) for f, m, sd in parts])
+        return rep, synth.embeddings(rep.seqs, rep.lens, 64)
+
+    A, eA = batch([(150, 8, 21), (100, 6, 22)])            # 1200 + 600 sequences
+    B, eB = batch([(100, 9, 23), (150, 6, 24)])            # 900 + 900: other boundaries
+    assert A.n == B.n
+    say(f"pipeline graph on a new batch n={A.n}")
+    pipe = Pipeline(A.seqs, A.lens, A.vgene, A.family, eA, S, *W, cfg=cfg, rep_offsets=A.rep_offsets)
+    pipe.step(check_capacity=True)
+    P_A = pipe.P
+    pipe.fit_capacity(slack=1.0)                              # room for a batch with more pairs
+    cap = pipe.cap
+    pipe.capture()
+    pipe.load(seqs=B.seqs, lens=B.lens, vgene=B.vgene, family=B.family, emb=eB, rep_offsets=B.rep_offsets)
+    for k in range(2):
+        pipe.fused.zero_()
+        torch.cuda.synchronize()
+        pipe.replay()
+        torch.cuda.synchronize()
+        P_B, status = pipe.graph_status()
+        assert status == 0 and P_B != P_A and P_B <= cap
+        ref = Pipeline(B.seqs, B.lens, B.vgene, B.family, eB, S, *W, cfg=cfg, rep_offsets=B.rep_offsets, cap=cap)
+        ref.step()
+        assert ref.graph_status() == (P_B, 0)
+        assert torch.equal(pipe.sig, ref.sig)
+        assert torch.equal(pipe.pairs[:P_B], ref.pairs[:P_B])
+        assert torch.equal(pipe.scores[:P_B], ref.scores[:P_B])
+        assert torch.equal(pipe.fused[:P_B], ref.fused[:P_B])
+        for a, b in zip(pipe.grads[:4], ref.grads[:4]):
+            assert torch.equal(a, b)
+        assert torch.allclose(pipe.grads[4], ref.grads[4], rtol=1e-5, atol=1e-7)
+        assert abs(pipe.loss.item() - ref.loss.item()) <= 1e-12 * abs(ref.loss.item())
+        del ref
+    sig = omh.signatures(B.seqs, B.lens, 64, synth.HASH_SEED)
+    pairs = olsh.candidates_grouped(sig, 16, 4, rep_offsets=B.rep_offsets)
+    assert np.array_equal(pipe.pairs[:P_B].cpu().numpy().astype(np.int64), pairs)
+    assert np.array_equal(pipe.scores[:P_B].cpu().numpy(), osw.scores_pairs(B.seqs, B.lens, pairs, S))
+    # a batch with more candidates than the capacity: flagged, with its exact count
+    C = synth.concat([synth.tiny(n_families=30, fam_size=40, seed=25), synth.tiny(n_families=30, fam_size=20, seed=26)])
+    assert C.n == A.n
+    sigC = omh.signatures(C.seqs, C.lens, 64, synth.HASH_SEED)
+    P_C = olsh.candidates_grouped(sigC, 16, 4, rep_offsets=C.rep_offsets).shape[0]
+    assert P_C > cap
+    pipe.load(seqs=C.seqs, lens=C.lens, vgene=C.vgene, family=C.family,
+              emb=synth.embeddings(C.seqs, C.lens, 64), rep_offsets=C.rep_offsets)
+    say(f"pipeline graph overflow P={P_C} cap={cap}")
+    pipe.replay()
+    torch.cuda.synchronize()
+    assert pipe.graph_status() == (P_C, 4)
+
+
 def test_knobs_never_change_results():
     """Launch-shape knobs (the autotuner's search space) leave every result unchanged."""
     from paper_2602_17330_amd import autotune
