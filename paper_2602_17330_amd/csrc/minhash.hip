@@ -6,12 +6,15 @@
 // residue) from the caller's seed.  The signature is the unsigned minimum over the set of
 // distinct 3-mers; taking the minimum over every 3-mer position gives the same value.
 //
-// Mapping to CDNA4: one wave per sequence, lane l owns hash functions l + 64 j (j < J).
-// Every block regenerates the 60*M table words into LDS as separate hi and lo 32-bit
-// planes, laid out [pos][residue][lane][j], so that a lookup with a wave-uniform residue
-// reads consecutive 4*J-byte words (no bank conflicts).  Rows reach a wave in groups of
+// Mapping to CDNA4: one wave per sequence, lane l owns hash functions l + 64 q.  Every block
+// regenerates the 60*M table words into LDS (full hi and lo planes, plus the top 16 bits of
+// the hi halves packed two hash functions to a word), laid out [residue][position][lane] so
+// that a lookup with a wave-uniform residue reads consecutive words (no bank conflicts) and
+// one address per residue serves all three positions.  Rows reach a wave in groups of
 // consecutive sequences, one coalesced load per group issued a group ahead.  Stores are
 // 512-byte coalesced rows of sig.
+#include <type_traits>
+
 #include "common.h"
 
 namespace subquad {
@@ -26,7 +29,6 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t q) {
 }
 
 constexpr int kMinhashBlock = 1024;
-constexpr uint32_t kPosMask = 63u;  // shingle positions 0..61 (stride <= 64)
 
 // Median of three unsigned words (one VALU instruction).
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
@@ -35,52 +37,70 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c) {
     return r;
 }
 
-// A lane's J consecutive table words in one LDS access (8 or 16 bytes for J = 2 or 4).
-template <int J>
-__device__ __forceinline__ void lds_words(const uint32_t *p, uint32_t (&v)[J]) {
-    if constexpr (J == 1) {
+// a ^ b ^ c as one VALU instruction (v_bitop3 with the three-way XOR truth table).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+// A lane's JP consecutive table words in one LDS access (4 or 8 bytes).
+template <int JP>
+__device__ __forceinline__ void lds_words(const uint32_t *p, uint32_t (&v)[JP]) {
+    if constexpr (JP == 1) {
         v[0] = p[0];
-    } else if constexpr (J == 2) {
+    } else {
         const uint2 t = *reinterpret_cast<const uint2 *>(p);
         v[0] = t.x;
         v[1] = t.y;
-    } else {
-        const uint4 t = *reinterpret_cast<const uint4 *>(p);
-        v[0] = t.x;
-        v[1] = t.y;
-        v[2] = t.z;
-        v[3] = t.w;
     }
 }
 
-// The signature word is compared as (hi, lo) 32-bit halves.  The streaming pass reads only
-// the hi halves of the tables; per hash function it keeps the smallest and second smallest
-// of the words (top 26 bits of hi | shingle position): m1 and m2 (v_med3 of m1, m2 and the
-// new word), so m1 carries its own position.  When m1 and m2 differ in the top 26 bits, the
-// shingle at m1's position has the strictly smallest hi half, hence the minimum hash, whose
-// full 64 bits are read once at the end.  Otherwise (a repeated 3-mer, or two 3-mers whose
-// hashes agree in those bits) that lane redoes the sequence with full 64-bit words, taking
-// the residues from the row words the wave already holds.
-template <int J>
+// Lane l owns the 2 JP hash functions t = l + 64 q (q < 2 JP).  Three LDS tables, each
+// laid out [residue][position][lane][...] so that one address per residue serves the three
+// position tables (their offsets are immediates):
+//   Q  [20][3][64][JP]   packed top halves: word jp holds the top 16 bits of the hi half of
+//                        hash q = 2 jp (low 16 bits) and of hash q = 2 jp + 1 (high 16 bits);
+//   Hh, Hl [20][3][2 JP][64]   the full hi and lo halves of every hash (a lane's words 4
+//                        bytes apart, so that the winners' lookups are conflict-free).
+// The streaming pass XORs three packed words per shingle (two hash functions at once) and
+// keeps, per hash function, the smallest and second smallest of the keys
+// (16 top bits << 16 | the shingle's 3-mer code a << 10 | b << 5 | c): m1 and m2 (v_med3
+// of m1, m2 and the new key).  When m1 and m2 differ in their top 16 bits, m1's 3-mer has
+// strictly the smallest hi half of all the sequence's 3-mers, hence the minimum hash, whose
+// full 64 bits are read once from its code.  Otherwise (the same 3-mer twice, or two 3-mers
+// whose hashes share those 16 bits) that lane redoes the sequence with full 64-bit words.
+template <int JP>
 __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const uint8_t *__restrict__ seqs, const int32_t *__restrict__ lens, int64_t n, int32_t stride,
     int32_t M, uint64_t seed, uint64_t *__restrict__ sig) {
+    constexpr int J = 2 * JP;                     // hash functions per lane
+    constexpr int kHWords = 20 * 3 * 64 * J;      // one full plane
+    constexpr int kQWords = 20 * 3 * 64 * JP;
+    constexpr int kResH = 3 * 64 * J, kPosH = 64 * J;    // strides (words) in Hh / Hl
+    constexpr int kResQ = 3 * 64 * JP, kPosQ = 64 * JP;  // strides (words) in Q
     extern __shared__ uint32_t lds[];
-    constexpr int kEntries = 3 * 20 * 64 * J;  // [pos][residue][lane][j]
-    uint32_t *Thi = lds;
-    uint32_t *Tlo = lds + kEntries;
-    for (int e = threadIdx.x; e < kEntries; e += blockDim.x) {
-        int j = e % J;
-        int l = (e / J) % 64;
-        int pr = e / (J * 64);  // pos * 20 + residue
-        int t = l + 64 * j;
+    uint32_t *Hh = lds;
+    uint32_t *Hl = lds + kHWords;
+    uint32_t *Q = lds + 2 * kHWords;
+    for (int e = threadIdx.x; e < kHWords; e += blockDim.x) {
+        const int l = e % 64;
+        const int q = (e / 64) % J;
+        const int rp = e / (J * 64);  // residue * 3 + position
+        const int t = l + 64 * q;
         uint64_t v = ~0ull;
         if (t < M) {
-            int pos = pr / 20, res = pr % 20;
+            const int res = rp / 3, pos = rp % 3;
             v = splitmix64_at(seed, ((uint64_t)t * 3 + pos) * 20 + res);
         }
-        Thi[e] = (uint32_t)(v >> 32);
-        Tlo[e] = (uint32_t)v;
+        Hh[e] = (uint32_t)(v >> 32);
+        Hl[e] = (uint32_t)v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kQWords; e += blockDim.x) {
+        const int jp = e % JP;
+        const int l = (e / JP) % 64;
+        const int base = (e / (JP * 64)) * (64 * J) + 2 * jp * 64 + l;  // hash q = 2 jp of that row in Hh
+        Q[e] = (Hh[base] >> 16) | (Hh[base + 64] & 0xFFFF0000u);
     }
     __syncthreads();
 
@@ -88,16 +108,16 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     const int64_t wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) +
                          (int64_t)blockIdx.x * (blockDim.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    constexpr int kRole = 20 * 64 * J;  // words between position tables
-    const uint32_t *Hl = Thi + lane * J;
-    const uint32_t *Ll = Tlo + lane * J;
+    const uint32_t *Ql = Q + lane * JP;
+    const uint32_t *Hhl = Hh + lane;
+    const uint32_t *Hll = Hl + lane;
 
     // Sequences go to waves in groups of G consecutive rows, G = 64 / D with D = stride / 4
     // words per row: one coalesced dword load per lane brings a whole group (lane k D + w holds
-    // word w of row k), issued a group ahead; the hashing loop reads words with readlane at
-    // wave-uniform indices, and each lane fetches the words around its winning shingle from
-    // the lane that holds them (ds_bpermute).  The wait for that load (which on this ISA also
-    // waits for the signature stores) thus comes once per group.
+    // word w of row k), issued a group ahead.  Each lane then prepares, for the four residue
+    // positions of its word, the LDS byte offsets of their table rows and the 3-mer codes of
+    // the shingles starting there (two 16-bit values per word); the hashing loop broadcasts
+    // them with readlane, so the per-shingle work is vector work with scalar operands.
     const int D = stride >> 2;
     const int G = 64 / D;
     const int64_t ngroups = ceil_div(n, (int64_t)G);
@@ -113,91 +133,120 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
             if (lane < G && base + lane < n) nlen = lens[base + lane];
         }
     };
+    // key = (16 hash bits << 16) | 3-mer code, from a packed hash word h and a packed code
+    // word s (v_perm byte selectors: bytes 4..7 are h's, 0..3 are s's)
+    const uint32_t sel_lo_c0 = 0x05040100u, sel_lo_c1 = 0x05040302u;  // hash q = 2 jp
+    const uint32_t sel_hi_c0 = 0x07060100u, sel_hi_c1 = 0x07060302u;  // hash q = 2 jp + 1
+    const char *Qb = reinterpret_cast<const char *>(Ql);
     fetch(wave);
     for (int64_t g = wave; g < ngroups; g += nwaves) {
         const uint32_t rowv = nrow;
         const int lenv = nlen;
         fetch(g + nwaves);
+        // this lane's residue positions 4w .. 4w + 5 (the next word from the next lane;
+        // positions past a row only ever feed shingles past its length)
+        const uint32_t nxt = (uint32_t)__shfl_down((int)rowv, 1, 64);
+        uint32_t r[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) r[e] = min(((e < 4 ? rowv >> (8 * e) : nxt >> (8 * (e - 4)))) & 0xFFu, 19u);
+        constexpr uint32_t kRowBytes = 4u * kResQ;  // one residue's table rows
+        const uint32_t off01 = r[0] * kRowBytes | (r[1] * kRowBytes) << 16;
+        const uint32_t off23 = r[2] * kRowBytes | (r[3] * kRowBytes) << 16;
+        uint32_t cd[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cd[e] = (r[e] << 10) | (r[e + 1] << 5) | r[e + 2];
+        const uint32_t code01 = cd[0] | cd[1] << 16, code23 = cd[2] | cd[3] << 16;
         const int64_t base = g * G;
         const int gn = (int)min((int64_t)G, n - base);
         for (int k = 0; k < gn; ++k) {
             const int64_t i = base + k;
-            const int L = __builtin_amdgcn_readlane(lenv, k);
+            const int L = min(max(__builtin_amdgcn_readlane(lenv, k), 0), stride);
             const int kD = k * D;
             const int nsh = L - 2;  // shingles
+            uint64_t *out = sig + i * (int64_t)M;
+            if (nsh <= 0) {  // no 3-mer (a length below 3 breaks the contract): the empty minimum
+#pragma unroll
+                for (int q = 0; q < J; ++q)
+                    if (lane + 64 * q < M) out[lane + 64 * q] = ~0ull;
+                continue;
+            }
             uint32_t m1[J], m2[J];
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                m1[j] = ~0u;
-                m2[j] = ~0u;
+            for (int q = 0; q < J; ++q) {
+                m1[q] = ~0u;
+                m2[q] = ~0u;
             }
-            // Four shingles per iteration: residues q .. q+5 come from two row words, and all
-            // twelve lookups are issued before any is used.
-#pragma unroll 1
-            for (int q = 0; q < nsh; q += 4) {
-                const int w = q >> 2;
-                const uint32_t w0 = __builtin_amdgcn_readlane(rowv, kD + w);
-                const uint32_t w1 = w + 1 < D ? __builtin_amdgcn_readlane(rowv, kD + w + 1) : 0u;
-                uint32_t off[6];
+            // Four shingles per iteration (positions q0 .. q0+5, from row words w and w + 1):
+            // one LDS address per position serves its three position tables, and all twelve
+            // lookups are issued before any is used.  `live` shingles of the four count.
+            auto iter = [&](int q0, auto live) {
+                const int w = q0 >> 2;
+                const uint32_t so01 = __builtin_amdgcn_readlane(off01, kD + w);
+                const uint32_t so23 = __builtin_amdgcn_readlane(off23, kD + w);
+                const uint32_t so45 = w + 1 < D ? __builtin_amdgcn_readlane(off01, kD + w + 1) : 0u;
+                const uint32_t sc01 = __builtin_amdgcn_readlane(code01, kD + w);
+                const uint32_t sc23 = __builtin_amdgcn_readlane(code23, kD + w);
+                const uint32_t so[6] = {so01 & 0xFFFFu, so01 >> 16, so23 & 0xFFFFu, so23 >> 16, so45 & 0xFFFFu,
+                                        so45 >> 16};
+                const uint32_t *A[6];
 #pragma unroll
-                for (int e = 0; e < 6; ++e) {
-                    uint32_t c = e < 4 ? (w0 >> (8 * e)) & 0xFFu : (w1 >> (8 * (e - 4))) & 0xFFu;
-                    off[e] = (c < 20u ? c : 19u) * (64 * J);
-                }
-                uint32_t h[4][J];
+                for (int e = 0; e < 6; ++e) A[e] = reinterpret_cast<const uint32_t *>(Qb + so[e]);
+                uint32_t h[4][JP];
 #pragma unroll
                 for (int sh = 0; sh < 4; ++sh) {
-                    uint32_t t0[J], t1[J], t2[J];
-                    lds_words<J>(Hl + off[sh], t0);
-                    lds_words<J>(Hl + kRole + off[sh + 1], t1);
-                    lds_words<J>(Hl + 2 * kRole + off[sh + 2], t2);
+                    uint32_t t0[JP], t1[JP], t2[JP];
+                    lds_words<JP>(A[sh], t0);
+                    lds_words<JP>(A[sh + 1] + kPosQ, t1);
+                    lds_words<JP>(A[sh + 2] + 2 * kPosQ, t2);
 #pragma unroll
-                    for (int j = 0; j < J; ++j) h[sh][j] = t0[j] ^ t1[j] ^ t2[j];
+                    for (int jp = 0; jp < JP; ++jp) h[sh][jp] = xor3(t0[jp], t1[jp], t2[jp]);
                 }
-                const int live = min(4, nsh - q);  // wave-uniform
 #pragma unroll
                 for (int sh = 0; sh < 4; ++sh) {
                     if (sh < live) {
+                        const uint32_t sc = sh < 2 ? sc01 : sc23;
+                        const uint32_t sa = (sh & 1) ? sel_lo_c1 : sel_lo_c0, sb = (sh & 1) ? sel_hi_c1 : sel_hi_c0;
 #pragma unroll
-                        for (int j = 0; j < J; ++j) {
-                            // top 26 bits of the hi half, shingle position in the low 6
-                            const uint32_t v = (h[sh][j] & ~kPosMask) | (uint32_t)(q + sh);
-                            m2[j] = umed3(m1[j], m2[j], v);
-                            m1[j] = min(m1[j], v);
+                        for (int jp = 0; jp < JP; ++jp) {
+                            const uint32_t ka = __builtin_amdgcn_perm(h[sh][jp], sc, sa);  // hash q = 2 jp
+                            const uint32_t kb = __builtin_amdgcn_perm(h[sh][jp], sc, sb);  // hash q = 2 jp + 1
+                            m2[2 * jp] = umed3(m1[2 * jp], m2[2 * jp], ka);
+                            m1[2 * jp] = min(m1[2 * jp], ka);
+                            m2[2 * jp + 1] = umed3(m1[2 * jp + 1], m2[2 * jp + 1], kb);
+                            m1[2 * jp + 1] = min(m1[2 * jp + 1], kb);
                         }
                     }
                 }
-            }
-            uint64_t *out = sig + i * (int64_t)M;
+            };
+            int q0 = 0;
+#pragma unroll 1
+            for (; q0 + 4 <= nsh; q0 += 4) iter(q0, std::integral_constant<int, 4>{});
+            if (q0 < nsh) iter(q0, nsh - q0);  // the last, partial, iteration
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int t = lane + 64 * j;
-                // lo half of the winning shingle: its three residues, from the lanes holding
-                // words position/4 and position/4 + 1 of this row
-                const uint32_t a = m1[j] & kPosMask, wa = a >> 2;
-                const uint32_t lo0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((kD + wa) * 4), (int)rowv);
-                uint32_t hi0 = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((kD + wa + 1) * 4), (int)rowv);
-                if (wa + 1 >= (uint32_t)D) hi0 = 0u;
-                const uint32_t tri = (uint32_t)((((uint64_t)hi0 << 32) | lo0) >> (8 * (a & 3u)));
-                const uint32_t a0 = min(tri & 0xFFu, 19u), a1 = min((tri >> 8) & 0xFFu, 19u),
-                               a2 = min((tri >> 16) & 0xFFu, 19u);
-                const int o0 = a0 * (64 * J) + j, o1 = kRole + a1 * (64 * J) + j, o2 = 2 * kRole + a2 * (64 * J) + j;
-                const uint32_t hi = Hl[o0] ^ Hl[o1] ^ Hl[o2];  // the full hi half (its low 6 bits were replaced)
-                const uint32_t lo = Ll[o0] ^ Ll[o1] ^ Ll[o2];
-                uint64_t best = ((uint64_t)hi << 32) | lo;
-                if ((m1[j] >> 6) == (m2[j] >> 6)) {  // a tie in the top bits: exact 64-bit minimum over every position
+            for (int q = 0; q < J; ++q) {
+                const int t = lane + 64 * q;
+                // the winner's full 64 bits from its code (nsh >= 1, so m1 holds a real key
+                // and every field is a residue code below 20)
+                const uint32_t a0 = (m1[q] >> 10) & 31u, a1 = (m1[q] >> 5) & 31u, a2 = m1[q] & 31u;
+                const char *hb = reinterpret_cast<const char *>(Hhl + 64 * q);
+                const uint32_t *p0 = reinterpret_cast<const uint32_t *>(hb + a0 * (4 * kResH));
+                const uint32_t *p1 = reinterpret_cast<const uint32_t *>(hb + a1 * (4 * kResH)) + kPosH;
+                const uint32_t *p2 = reinterpret_cast<const uint32_t *>(hb + a2 * (4 * kResH)) + 2 * kPosH;
+                uint64_t best = ((uint64_t)xor3(p0[0], p1[0], p2[0]) << 32) |
+                                xor3(p0[kHWords], p1[kHWords], p2[kHWords]);  // hi, then the lo plane
+                if ((m1[q] ^ m2[q]) < 0x10000u) {  // a tie in the top bits: exact 64-bit minimum
                     best = ~0ull;
-                    for (int q = 0; q + 3 <= L; ++q) {  // residues from the row words (no memory access)
-                        const int w = q >> 2;
+                    for (int p = 0; p + 3 <= L; ++p) {  // residues from the row words (no memory access)
+                        const int w = p >> 2;
                         const uint32_t wl = __builtin_amdgcn_readlane(rowv, kD + w);
                         const uint32_t wh = w + 1 < D ? __builtin_amdgcn_readlane(rowv, kD + w + 1) : 0u;
-                        const uint32_t tq = (uint32_t)((((uint64_t)wh << 32) | wl) >> (8 * (q & 3)));
+                        const uint32_t tq = (uint32_t)((((uint64_t)wh << 32) | wl) >> (8 * (p & 3)));
                         const uint32_t b0 = min(tq & 0xFFu, 19u);
                         const uint32_t b1 = min((tq >> 8) & 0xFFu, 19u);
                         const uint32_t b2 = min((tq >> 16) & 0xFFu, 19u);
-                        const int e0 = b0 * (64 * J) + j, e1 = kRole + b1 * (64 * J) + j,
-                                  e2 = 2 * kRole + b2 * (64 * J) + j;
-                        uint64_t hh = ((uint64_t)(Hl[e0] ^ Hl[e1] ^ Hl[e2]) << 32) | (Ll[e0] ^ Ll[e1] ^ Ll[e2]);
+                        const int e0 = b0 * kResH + 64 * q, e1 = b1 * kResH + kPosH + 64 * q,
+                                  e2 = b2 * kResH + 2 * kPosH + 64 * q;
+                        const uint64_t hh = ((uint64_t)(Hhl[e0] ^ Hhl[e1] ^ Hhl[e2]) << 32) | (Hll[e0] ^ Hll[e1] ^ Hll[e2]);
                         best = hh < best ? hh : best;
                     }
                 }
@@ -207,22 +256,22 @@ __global__ __launch_bounds__(kMinhashBlock) void minhash3_kernel(
     }
 }
 
-template <int J>
+template <int JP>
 static int launch_minhash(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, int32_t M,
                           uint64_t seed, uint64_t *sig, hipStream_t st) {
-    const size_t lds = 2 * sizeof(uint32_t) * 3 * 20 * 64 * J;
+    const size_t lds = sizeof(uint32_t) * (2 * 20 * 3 * 64 * 2 * JP + 20 * 3 * 64 * JP);
     static bool attr_set = false;
     if (!attr_set) {
-        SQ_HIP(hipFuncSetAttribute((const void *)minhash3_kernel<J>,
+        SQ_HIP(hipFuncSetAttribute((const void *)minhash3_kernel<JP>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
     const int waves_per_block = kMinhashBlock / kWave;
-    const int per_cu = J <= 2 ? std::min(knob(SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU), 2) : 1;  // LDS bound
+    const int per_cu = JP == 1 ? std::min(knob(SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU), 2) : 1;  // LDS bound
     const int64_t groups = ceil_div(n, (int64_t)(64 / (stride / 4)));  // rows per wave group: 64 / (stride / 4)
     int64_t blocks = std::min<int64_t>(ceil_div(groups, waves_per_block), (int64_t)device_cus() * per_cu);
     ProfScope prof("minhash3_kernel", st);
-    minhash3_kernel<J><<<(unsigned)blocks, kMinhashBlock, lds, st>>>(seqs, lens, n, stride, M, seed, sig);
+    minhash3_kernel<JP><<<(unsigned)blocks, kMinhashBlock, lds, st>>>(seqs, lens, n, stride, M, seed, sig);
     SQ_LAUNCHED("minhash3_kernel");
     return SUBQUAD_OK;
 }
@@ -243,7 +292,6 @@ extern "C" int subquad_minhash(const uint8_t *seqs, const int32_t *lens, int64_t
     SQ_REQUIRE(((uintptr_t)seqs & 3) == 0, SUBQUAD_ERR_ARG, "seqs must be 4-byte aligned");
     if (n == 0) return SUBQUAD_OK;
     hipStream_t st = as_stream(stream);
-    if (M <= 64) return launch_minhash<1>(seqs, lens, n, stride, M, seed, sig, st);
-    if (M <= 128) return launch_minhash<2>(seqs, lens, n, stride, M, seed, sig, st);
-    return launch_minhash<4>(seqs, lens, n, stride, M, seed, sig, st);
+    if (M <= 128) return launch_minhash<1>(seqs, lens, n, stride, M, seed, sig, st);
+    return launch_minhash<2>(seqs, lens, n, stride, M, seed, sig, st);
 }
