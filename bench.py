@@ -39,7 +39,8 @@ MFMA_F32_PEAK_TFLOPS = 157.3  # dense fp32 matrix-core peak
 KERNEL_SOURCES = {
     "gate_bwd_kernel": ["gate.hip", "gate_util.h"], "gate_fwd_kernel": ["gate.hip", "gate_util.h"],
     "gate_cos_bwd_j_kernel": ["gate_util.h"], "gate_wgrad_kernel": ["gate.hip", "gate_util.h"],
-    "lsh_emit_small_kernel": ["lsh.hip"], "lsh_emit_kernel": ["lsh.hip"], "lsh_keys_kernel": ["lsh.hip"],
+    "lsh_emit_small_kernel": ["lsh.hip"], "lsh_emit_long_kernel": ["lsh.hip"], "lsh_keys_kernel": ["lsh.hip"],
+    "lsh_class_small_kernel": ["lsh.hip"], "lsh_class_long_kernel": ["lsh.hip"],
     "lsh_runs_kernel": ["lsh.hip"], "minhash3_kernel": ["minhash.hip"], "align_kernel": ["align.hip"],
     "radix_scatter_kernel": ["radix.hip"], "radix_hist_kernel": ["radix.hip"],
     "proto_fwd_kernel": ["proto.hip"], "proto_bwd_rows_kernel": ["proto.hip"],
@@ -426,7 +427,7 @@ def bench_batch64(a, torch, sq):
     linear footprint behind the prefilter); each leg runs batch after batch, so the
     reported times are sums over the planned batches."""
     import synth
-    from paper_2602_17330_amd import autotune
+    from paper_2602_17330_amd import _lib, autotune
     from paper_2602_17330_amd.batching import bytes_per_sequence, plan_batches
     from paper_2602_17330_amd.pipeline import PathConfig, Pipeline
     t = time.perf_counter()
@@ -444,6 +445,7 @@ def bench_batch64(a, torch, sq):
         f"{[int(sizes[b].sum()) for b in plan]} sequences")
     t_per = t_big = t_graph = 0.0
     P_tot = cells = 0
+    kern_per, kern_big = {}, {}
     tuned = None
     per_stage_ms = np.zeros(5)
     for bi, reps in enumerate(plan):
@@ -466,6 +468,10 @@ def bench_batch64(a, torch, sq):
                 pp.step()
 
         t_per += time_region(torch, run_per, a.steps, a.warmup)
+        _lib.profile_enable(True)
+        run_per()
+        kern_per = _merge_kernels(kern_per, _lib.profile_report())
+        _lib.profile_enable(False)
         del per, pp
         torch.cuda.empty_cache()
         # (ii) one launch per stage over all repertoires of the batch
@@ -484,6 +490,10 @@ def bench_batch64(a, torch, sq):
         big.step(events=ev[1:])
         torch.cuda.synchronize()
         per_stage_ms += np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(5)])
+        _lib.profile_enable(True)
+        big.step()
+        kern_big = _merge_kernels(kern_big, _lib.profile_report())
+        _lib.profile_enable(False)
         big.capture()
         t_graph += time_region(torch, big.replay, a.steps, a.warmup)
         status = big.graph_status()
@@ -508,9 +518,18 @@ def bench_batch64(a, torch, sq):
         "per_repertoire_ms": t_per * 1e3, "batched_eager_ms": t_big * 1e3, "batched_graph_ms": t_graph * 1e3,
         "batched_stage_ms": {s: float(m) for s, m in zip(("minhash", "lsh", "self", "align", "gate"), per_stage_ms)},
         "speedup_graph_vs_per_repertoire": t_per / t_graph, "speedup_eager_vs_per_repertoire": t_per / t_big,
+        # one step of each leg with every main kernel timed (HIP events): (launches, total ms)
+        "kernels_per_repertoire": kern_per, "kernels_batched": kern_big,
         "autotune": tuned,
     }
     print(json.dumps(out), flush=True)
+
+
+def _merge_kernels(acc, rep):
+    for k, (c, ms) in rep.items():
+        c0, m0 = acc.get(k, (0, 0.0))
+        acc[k] = (c0 + c, m0 + ms)
+    return acc
 
 
 def main():
@@ -598,11 +617,11 @@ def main():
     # algorithmic bytes (or int32 ops) of ONE launch of each kernel
     alg = {
         "minhash3_kernel": ("hbm", n * (rep.stride + 4) + n * M * 8),
-        "lsh_keys_kernel": ("hbm", n * b * r * 8 + recs * 8 + recs),
+        "lsh_keys_kernel": ("hbm", n * b * r * 8 + recs * 8 + recs * 4),
         "sort_records_scatter": ("hbm", 2 * recs * 8),
         "sort_records_hist": ("hbm", recs * 8),
-        # emission: every record read once, every pair key written once (short runs; the
-        # long runs' remainder has no separate figure)
+        # short-run emission: every record read once, every pair key written once (the class
+        # rows each visited pair reads are counted by the profiles, not here)
         "lsh_emit_small_kernel": ("hbm", recs * 8 + 8 * P),
         "sort_pairs_scatter": ("hbm", 2 * P * 8),
         "sort_pairs_hist": ("hbm", P * 8),

@@ -61,7 +61,7 @@ enum subquad_knob {
     SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU = 0,  /* persistent MinHash blocks per CU (default 2) */
     SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU = 1,    /* persistent alignment blocks per CU (default 4) */
     SUBQUAD_KNOB_GATE_GROUPS_PER_CU = 2,     /* 16-lane pair groups per CU (default 64)       */
-    SUBQUAD_KNOB_EMIT_THREADS = 3,           /* LSH run-scan block size (default 512)          */
+    SUBQUAD_KNOB_EMIT_THREADS = 3,           /* LSH long-run emission block size (512)         */
     SUBQUAD_KNOB_COUNT = 4
 };
 int subquad_set_knob(int32_t knob, int32_t value);  /* SUBQUAD_ERR_ARG for an unknown knob */

@@ -20,7 +20,7 @@ CANDIDATES = {
     "minhash_blocks_per_cu": [1, 2],
     "align_blocks_per_cu": [2, 4, 8, 16],
     "gate_groups_per_cu": [16, 32, 64, 128, 256],
-    "emit_threads": [128, 256, 512],
+    "emit_threads": [256, 512, 1024],
 }
 STAGE_OF = {"minhash_blocks_per_cu": "minhash", "align_blocks_per_cu": "align",
             "gate_groups_per_cu": "gate", "emit_threads": "lsh"}

@@ -15,8 +15,8 @@
 // l, l + 16, ...; dot products and the logit are reduced with 16-wide shuffles.  A group
 // walks a contiguous chunk of the (row-sorted) pair list, so e_i, |e_i| and, in the
 // backward, the gradient of e_i stay in registers while the first index repeats.  Weight
-// gradients accumulate per lane in float64 and are reduced per block, then once per block
-// into a float64 workspace.
+// gradients are summed in float32 over each batch of 16 pairs, in float64 per block, and over
+// blocks in a fixed order (gate_wgrad_kernel, gate_ws_reduce_kernel).
 #include "gate_util.h"
 #include "radix.h"
 

@@ -6,18 +6,23 @@
 // sig[i][beta*r .. beta*r + r) and sig[j][...] are exactly equal.  Steps:
 //   1. band records: for every (beta, i) a 64-bit mix of (tuple, repertoire); the record is
 //      (top bits of the mix | beta) << 32 | (beta * n + i), written band-major (beta in the
-//      word's low bits when the sort key leaves them free).  An 8-bit
-//      fingerprint of every (i, beta) mix goes to a row-major table F[n][b].
+//      word's low bits when the sort key leaves them free).  Every (i, beta) also gets a
+//      class id in a row-major table C[n][b], at first its own record number beta * n + i.
 //   2. stable radix sort of the records on their mix bits (log2 n + 4 rounded up to whole
 //      bytes, at most 32: 24 for n <= 2^20; the bits below are cleared).  Stability keeps
 //      records with equal mix bits in (beta, i) order, so each bucket (equal mix bits, equal
 //      band) is a contiguous run with ascending i.
-//   3. run scan: for every record, every later record of its run is a potential partner.
-//      The pair is kept only if (a) both rows are in one repertoire, (b) the band tuples are
-//      exactly equal, and (c) beta is the FIRST band in which the tuples are equal (earlier
-//      bands are tested through F first and confirmed on the tuples), so each candidate is
-//      emitted exactly once.  Kept pairs are appended as keys (i << nb) | j.
-//   4. radix sort of the pair keys gives the canonical (i, j) order; then the pair list and
+//   3. runs: every run of >= 2 records is listed.  Equal tuples (of one repertoire) always
+//      share a run, so exact classes are formed inside runs: a member whose tuple and
+//      repertoire equal those of its run's first record takes that record's number as its
+//      class id, any other member the number of the first member equal to it.  Afterwards
+//      C[i][e] == C[j][e] holds exactly when i and j (of one repertoire) have equal tuples
+//      in band e.
+//   4. emission: every pair of records of a run is a potential partner; it is kept only in
+//      the FIRST band in which its tuples are equal (class ids equal in the run's band and
+//      different in every earlier one), so each candidate is emitted exactly once.  Kept
+//      pairs are appended as keys (i << nb) | j.
+//   5. radix sort of the pair keys gives the canonical (i, j) order; then the pair list and
 //      the CSR row offsets are written.
 // The mixing function only decides which records meet; equality is always decided on the
 // signature words themselves, so results never depend on hash collisions.
@@ -29,6 +34,12 @@ constexpr int kKeysTileSeqs = 64;
 constexpr int kKeysThreads = 256;
 constexpr int kKeysUnroll = 8;
 
+// Words per row of the class-id table C: b rounded up to whole 16-byte words, so that every
+// row is 16-byte aligned.
+__host__ __device__ inline int class_stride(int b) { return (b + 3) & ~3; }
+
+// 64-bit finaliser of MurmurHash3 (fmix64, Austin Appleby's published constants): a
+// bijective mix whose every output bit depends on every input bit.
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 33)) * 0xFF51AFD7ED558CCDull;
     z = (z ^ (z >> 33)) * 0xC4CEB9FE1A85EC53ull;
@@ -36,13 +47,14 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // Step 1. Block = 64 sequences x b bands.  Reads of the signature rows are contiguous
-// (item e = s * b + beta), record stores are contiguous per band (staged through LDS).
+// (item e = s * b + beta), record stores are contiguous per band (staged through LDS), and
+// the class-id rows C[i][0..b) are written in the same item order (contiguous).
 // R4: r == 4 with 16-byte aligned tuples, each read as two 16-byte loads.
 template <bool R4>
 __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     const uint64_t *__restrict__ sig, int64_t n, int32_t M, int32_t b, int32_t r,
     const int64_t *__restrict__ offs, int64_t R, uint32_t keep, uint32_t band_in_key, uint64_t *__restrict__ rec,
-    uint8_t *__restrict__ F) {
+    uint32_t *__restrict__ C) {
     extern __shared__ uint32_t keyhi[];  // [b][64]
     const int64_t i0 = (int64_t)blockIdx.x * kKeysTileSeqs;
     const int items = kKeysTileSeqs * b;
@@ -91,7 +103,7 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
             const int e = e0 + u * kKeysThreads + threadIdx.x;
             const int s = e / b, beta = e - s * b;
             keyhi[beta * kKeysTileSeqs + s] = ((uint32_t)(h[u] >> 32) & keep) | (band_in_key ? (uint32_t)beta : 0u);
-            F[(i0 + s) * b + beta] = (uint8_t)h[u];
+            C[(i0 + s) * class_stride(b) + beta] = (uint32_t)beta * (uint32_t)n + (uint32_t)(i0 + s);  // own class
         }
     }
     __syncthreads();
@@ -283,82 +295,173 @@ __global__ __launch_bounds__(kRunsThreads) void lsh_compact_kernel(
     }
 }
 
-__device__ __forceinline__ bool tuple_equal(const uint64_t *__restrict__ sig, int64_t M, int64_t i, int64_t j,
-                                            int beta, int r) {
+// Tuples of rows i and j equal in band beta, and i and j in one repertoire.
+__device__ __forceinline__ bool same_class(const uint64_t *__restrict__ sig, int64_t M, int r, int beta, int64_t i,
+                                           int64_t j, const int64_t *__restrict__ offs, int64_t R) {
     const uint64_t *a = sig + i * M + (int64_t)beta * r;
     const uint64_t *c = sig + j * M + (int64_t)beta * r;
     bool eq = true;
-    for (int k = 0; k < r; ++k) eq &= a[k] == c[k];
-    return eq;
+    if (r == 4 && (M & 1) == 0 && ((reinterpret_cast<uintptr_t>(sig) & 15) == 0)) {
+        const ulonglong2 *a2 = reinterpret_cast<const ulonglong2 *>(a), *c2 = reinterpret_cast<const ulonglong2 *>(c);
+        const ulonglong2 x0 = a2[0], x1 = a2[1], y0 = c2[0], y1 = c2[1];
+        eq = x0.x == y0.x && x0.y == y0.y && x1.x == y1.x && x1.y == y1.y;
+    } else {
+        for (int k = 0; k < r; ++k) eq &= a[k] == c[k];
+    }
+    return eq && (R <= 1 || rep_of(offs, R, i) == rep_of(offs, R, j));
 }
 
-// True when the tuples of i and j are equal in some band e < beta (fingerprints first,
-// signature words to confirm).
-__device__ __forceinline__ bool earlier_band(const uint64_t *__restrict__ sig, int64_t M, const uint8_t *__restrict__ F,
-                                             int b, int r, int64_t i, int64_t j, int beta) {
-    const uint8_t *Fi = F + i * b, *Fj = F + j * b;
-    if ((b & 3) == 0) {
-        const uint32_t *Wi = reinterpret_cast<const uint32_t *>(Fi);
-        const uint32_t *Wj = reinterpret_cast<const uint32_t *>(Fj);
-        for (int w = 0; 4 * w < beta; ++w) {
-            const uint32_t x = Wi[w] ^ Wj[w];
-            uint32_t z = (x - 0x01010101u) & ~x & 0x80808080u;  // flags equal bytes (and a few more)
-            const int live = beta - 4 * w;
-            if (live < 4) z &= (1u << (8 * live)) - 1u;
-            while (z) {
-                const int e = 4 * w + (__builtin_ctz(z) >> 3);
-                if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) return true;
-                z &= z - 1u;
+// Step 3b, class ids of the members of one run (records start .. start + m - 1 of the sorted
+// list, all of band beta): member k > 0 equal to the first record takes its record number;
+// a member that differs from it (two tuples met by chance in the mix bits) looks for the
+// first earlier member equal to it (whose own id is then the class's), else keeps its own.
+__device__ __forceinline__ void class_member(const uint64_t *__restrict__ srec, int64_t start, int64_t k, uint32_t la0,
+                                             int beta, uint32_t n32, const uint64_t *__restrict__ sig, int32_t M,
+                                             int32_t b, int32_t r, const int64_t *__restrict__ offs, int64_t R,
+                                             uint32_t *__restrict__ C) {
+    const uint32_t base = (uint32_t)beta * n32;
+    const uint32_t la = (uint32_t)srec[start + k];
+    const int64_t i = (int64_t)(la - base);
+    const int64_t i0 = (int64_t)(la0 - base);
+    uint32_t cls = la;
+    if (same_class(sig, M, r, beta, i, i0, offs, R)) {
+        cls = la0;
+    } else {
+        for (int64_t q = 1; q < k; ++q) {
+            const uint32_t lq = (uint32_t)srec[start + q];
+            if (same_class(sig, M, r, beta, i, (int64_t)(lq - base), offs, R)) {
+                cls = lq;
+                break;
             }
         }
-        return false;
     }
-    for (int e = 0; e < beta; ++e)
-        if (Fi[e] == Fj[e] && tuple_equal(sig, M, i, j, e, r)) return true;
-    return false;
+    if (cls != la) C[i * class_stride(b) + beta] = cls;
 }
 
-// Whether records la < lb of one bucket (band beta) make a candidate pair first found in
-// this band: same repertoire, equal tuples, no earlier band with equal tuples.
-__device__ __forceinline__ bool pair_found_here(uint32_t la, uint32_t lb, uint32_t n32, const uint64_t *__restrict__ sig,
-                                                int32_t M, int32_t b, int32_t r, const uint8_t *__restrict__ F,
-                                                const int64_t *__restrict__ offs, int64_t R, int64_t &i, int64_t &j) {
+// Short runs (the run list: (start << 32 | m), m = 0 for a slot whose run is long): one
+// thread per run.  The run's records, then every member's tuple, are loaded before any
+// comparison; member k's class is the first member k' < k with an equal tuple (k' = 0 but
+// in runs whose tuples met by chance in the mix bits), else its own record number.
+__global__ __launch_bounds__(256) void lsh_class_small_kernel(const uint64_t *__restrict__ srec, int64_t n,
+                                                              const uint64_t *__restrict__ sig, int32_t M, int32_t b,
+                                                              int32_t r, const int64_t *__restrict__ offs, int64_t R,
+                                                              const uint64_t *__restrict__ runs,
+                                                              const unsigned long long *__restrict__ counters,
+                                                              uint32_t *__restrict__ C) {
+    const int64_t nruns = (int64_t)counters[0];
+    const uint32_t n32 = (uint32_t)n;
+    const bool r4 = r == 4 && (M & 1) == 0 && ((reinterpret_cast<uintptr_t>(sig) & 15) == 0) && R <= 1;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nruns; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t run = runs[q];
+        const int m = (int)(uint32_t)run;
+        if (m < 2) continue;
+        const int64_t start = (int64_t)(run >> 32);
+        if (!r4) {
+            const uint32_t la0 = (uint32_t)srec[start];
+            const int beta = (int)(la0 / n32);
+            for (int k = 1; k < m; ++k) class_member(srec, start, k, la0, beta, n32, sig, M, b, r, offs, R, C);
+            continue;
+        }
+        uint32_t la[kSmallRun];
+#pragma unroll
+        for (int k = 0; k < kSmallRun; ++k) la[k] = k < m ? (uint32_t)srec[start + k] : 0u;
+        const int beta = (int)(la[0] / n32);
+        const uint32_t base = (uint32_t)beta * n32;
+        ulonglong2 t[kSmallRun][2];
+#pragma unroll
+        for (int k = 0; k < kSmallRun; ++k) {
+            if (k < m) {
+                const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(sig + (int64_t)(la[k] - base) * M + beta * 4);
+                t[k][0] = p[0];
+                t[k][1] = p[1];
+            } else {
+                t[k][0] = t[k][1] = make_ulonglong2(0ull, 0ull);
+            }
+        }
+#pragma unroll
+        for (int k = 1; k < kSmallRun; ++k) {
+            if (k >= m) break;
+            uint32_t cls = la[k];
+#pragma unroll
+            for (int q2 = 0; q2 < k; ++q2) {
+                const bool eq = t[k][0].x == t[q2][0].x && t[k][0].y == t[q2][0].y && t[k][1].x == t[q2][1].x &&
+                                t[k][1].y == t[q2][1].y;
+                if (eq) {
+                    cls = la[q2];
+                    break;
+                }
+            }
+            if (cls != la[k]) C[(int64_t)(la[k] - base) * class_stride(b) + beta] = cls;
+        }
+    }
+}
+
+// Long runs: one wave per run, lanes over its members.
+__global__ __launch_bounds__(256) void lsh_class_long_kernel(const uint64_t *__restrict__ srec, int64_t n,
+                                                             const uint64_t *__restrict__ sig, int32_t M, int32_t b,
+                                                             int32_t r, const int64_t *__restrict__ offs, int64_t R,
+                                                             const uint64_t *__restrict__ bruns,
+                                                             const unsigned long long *__restrict__ counters,
+                                                             uint32_t *__restrict__ C) {
+    const int64_t nruns = (int64_t)counters[2];
+    const uint32_t n32 = (uint32_t)n;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = wave; q < nruns; q += nwaves) {
+        const uint64_t run = bruns[q];
+        const int64_t m = (int64_t)(uint32_t)run;
+        const int64_t start = (int64_t)(run >> 32);
+        const uint32_t la0 = (uint32_t)srec[start];
+        const int beta = (int)(la0 / n32);
+        for (int64_t k = 1 + lane; k < m; k += 64) class_member(srec, start, k, la0, beta, n32, sig, M, b, r, offs, R, C);
+    }
+}
+
+// Whether records la < lb of one run (band beta) make a candidate pair first found in this
+// band: equal classes in beta, different classes in every earlier band.  i < j on return.
+__device__ __forceinline__ bool pair_first_here(uint32_t la, uint32_t lb, uint32_t n32, int32_t b,
+                                                const uint32_t *__restrict__ C, int64_t &i, int64_t &j) {
     const int beta = (int)(la / n32);
     if (beta >= b) return false;
     i = (int64_t)(la - (uint32_t)beta * n32);
     j = (int64_t)(lb - (uint32_t)beta * n32);  // i < j within a run
-    if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) return false;
-    if (!tuple_equal(sig, M, i, j, beta, r)) return false;
-    return !earlier_band(sig, M, F, b, r, i, j, beta);
-}
-
-// pair_found_here for 32 bands of 4 words with 16-byte aligned signature rows: the two
-// tuples and the two fingerprint rows are loaded together (16-byte loads), before any test.
-__device__ __forceinline__ bool pair_found_here_b32r4(uint32_t la, uint32_t lb, uint32_t n32,
-                                                      const uint64_t *__restrict__ sig, int32_t M,
-                                                      const uint8_t *__restrict__ F, const int64_t *__restrict__ offs,
-                                                      int64_t R, int64_t &i, int64_t &j) {
-    const int beta = (int)(la / n32);
-    if (beta >= 32) return false;
-    i = (int64_t)(la - (uint32_t)beta * n32);
-    j = (int64_t)(lb - (uint32_t)beta * n32);
-    const ulonglong2 *ti = reinterpret_cast<const ulonglong2 *>(sig + i * M + beta * 4);
-    const ulonglong2 *tj = reinterpret_cast<const ulonglong2 *>(sig + j * M + beta * 4);
-    const uint4 *fi = reinterpret_cast<const uint4 *>(F + i * 32);
-    const uint4 *fj = reinterpret_cast<const uint4 *>(F + j * 32);
-    const ulonglong2 a0 = ti[0], a1 = ti[1], c0 = tj[0], c1 = tj[1];
-    const uint4 fi0 = fi[0], fi1 = fi[1], fj0 = fj[0], fj1 = fj[1];
-    if (R > 1 && rep_of(offs, R, i) != rep_of(offs, R, j)) return false;
-    if (a0.x != c0.x || a0.y != c0.y || a1.x != c1.x || a1.y != c1.y) return false;
-    const uint32_t x[8] = {fi0.x ^ fj0.x, fi0.y ^ fj0.y, fi0.z ^ fj0.z, fi0.w ^ fj0.w,
-                           fi1.x ^ fj1.x, fi1.y ^ fj1.y, fi1.z ^ fj1.z, fi1.w ^ fj1.w};
+    const uint32_t *ci = C + i * class_stride(b), *cj = C + j * class_stride(b);
+    {
+        // the rows' words 0 .. beta as 16-byte loads, all issued before any test (rows are
+        // padded to whole 16-byte words)
+        const int wl = beta >> 2;
+        uint4 x[8], y[8];
+        const bool fits = b <= 32;
+        if (fits) {
 #pragma unroll
-    for (int w = 0; w < 8; ++w) {
-        if (4 * w >= beta) break;
-        for (int k = 0; k < 4 && 4 * w + k < beta; ++k)
-            if (((x[w] >> (8 * k)) & 0xFFu) == 0u && tuple_equal(sig, M, i, j, 4 * w + k, 4))
-                return false;  // equal tuples in an earlier band: the pair is emitted there
+            for (int w = 0; w < 8; ++w) {
+                if (w <= wl) {
+                    x[w] = reinterpret_cast<const uint4 *>(ci)[w];
+                    y[w] = reinterpret_cast<const uint4 *>(cj)[w];
+                } else {
+                    x[w] = y[w] = make_uint4(1u, 1u, 1u, 1u);  // past beta: never looked at
+                }
+            }
+            // equal in band beta and in no earlier band: word e of the rows' XOR is zero for
+            // e == beta and nonzero for every e < beta
+            bool ok = true;
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                const uint32_t e[4] = {x[w].x ^ y[w].x, x[w].y ^ y[w].y, x[w].z ^ y[w].z, x[w].w ^ y[w].w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int band = 4 * w + k;
+                    if (band < beta) ok &= e[k] != 0u;
+                    else if (band == beta) ok &= e[k] == 0u;
+                }
+            }
+            return ok;
+        }
     }
+    if (ci[beta] != cj[beta]) return false;
+    for (int e = 0; e < beta; ++e)
+        if (ci[e] == cj[e]) return false;
     return true;
 }
 
@@ -387,10 +490,8 @@ constexpr int kEmitBuf = 1024;                        // kept keys buffered per 
 // finds its run by bisection in LDS; k-th pair of a run: y = the largest y with
 // y(y-1)/2 <= k, x = k - y(y-1)/2).  Kept keys collect in LDS and leave in batches, one
 // global atomic per batch.
-template <bool B32R4>
 __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
-    const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
-    const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+    const uint64_t *__restrict__ srec, int64_t n, int32_t b, const uint32_t *__restrict__ C, int nb,
     const uint64_t *__restrict__ runs, const unsigned long long *__restrict__ counters, uint64_t *__restrict__ pkeys,
     int64_t cap, unsigned long long *__restrict__ count) {
     __shared__ uint32_t vend[kEmitRuns];  // inclusive prefix of the runs' pair counts
@@ -460,8 +561,7 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
                 const int64_t start = (int64_t)rsh[lo];
                 int64_t i = 0, j = 0;
                 const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
-                if (B32R4 ? pair_found_here_b32r4(la, lb, n32, sig, M, F, offs, R, i, j)
-                          : pair_found_here(la, lb, n32, sig, M, b, r, F, offs, R, i, j))
+                if (pair_first_here(la, lb, n32, b, C, i, j))
                     kbuf[atomicAdd(&kn, 1u)] = ((uint64_t)i << nb) | (uint64_t)j;
             }
             __syncthreads();
@@ -472,43 +572,65 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
     flush();
 }
 
-// Step 3b, long runs: one thread per (run, x < y) pair of records, the long runs' pairs
-// flattened by the prefix sum of their pair counts; k-th pair of a run: y = the largest y
-// with y(y-1)/2 <= k, x = k - y(y-1)/2.
-template <bool B32R4>
-__global__ __launch_bounds__(1024) void lsh_emit_kernel(
-    const uint64_t *__restrict__ srec, int64_t n, const uint64_t *__restrict__ sig, int32_t M, int32_t b, int32_t r,
-    const uint8_t *__restrict__ F, const int64_t *__restrict__ offs, int64_t R, int nb,
+// Long runs (more than kSmallRun records): one thread per (run, x < y) pair of records, the
+// long runs' pairs flattened by the prefix sum of their pair counts; k-th pair of a run:
+// y = the largest y with y(y-1)/2 <= k, x = k - y(y-1)/2.  A block's window of consecutive
+// pair indices spans few runs (a long run has at least kSmallRun (kSmallRun + 1) / 2 pairs):
+// one thread finds the window's first run in the global prefix, the window's runs and
+// offsets are staged in LDS, and every thread finds its run there.  A run's pairs are
+// consecutive, so its members' class-id rows are read from the cache by the threads that
+// share them.
+constexpr int kEmitWin = 64;  // runs staged per window
+__global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
+    const uint64_t *__restrict__ srec, int64_t n, int32_t b, const uint32_t *__restrict__ C, int nb,
     const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
+    static_assert((kSmallRun + 1) * kSmallRun / 2 * (kEmitWin - 1) >= 1024, "a window may span more runs");
     __shared__ uint32_t lcount;
     __shared__ unsigned long long gbase;
+    __shared__ uint64_t wrun[kEmitWin], wpoff[kEmitWin];
+    __shared__ int64_t wfirst;
     const int64_t nruns = (int64_t)counters[2];
     const uint64_t visits = (uint64_t)counters[1];
     const uint32_t n32 = (uint32_t)n;
     // block-uniform trip count: every thread reaches block_slot in every round
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < visits; base += (uint64_t)gridDim.x * blockDim.x) {
+        if (threadIdx.x == 0) {
+            int64_t lo = 0, hi = nruns - 1;  // last run with poff <= base
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (poff[mid] <= base) lo = mid; else hi = mid - 1;
+            }
+            wfirst = lo;
+        }
+        __syncthreads();
+        const int64_t first = wfirst;
+        for (int k = threadIdx.x; k < kEmitWin; k += blockDim.x) {
+            const int64_t q = first + k;
+            wpoff[k] = q < nruns ? poff[q] : ~0ull;
+            wrun[k] = q < nruns ? runs[q] : 0ull;
+        }
+        __syncthreads();
         const uint64_t t = base + threadIdx.x;
         bool want = false;
         int64_t i = 0, j = 0;
         if (t < visits) {
-            int64_t lo = 0, hi = nruns - 1;  // last run with poff <= t
+            int lo = 0, hi = kEmitWin - 1;  // last staged run with poff <= t
             while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (poff[mid] <= t) lo = mid; else hi = mid - 1;
+                const int mid = (lo + hi + 1) >> 1;
+                if (wpoff[mid] <= t) lo = mid; else hi = mid - 1;
             }
-            const uint64_t run = runs[lo];
+            const uint64_t run = wrun[lo];
             const uint64_t start = run >> 32;
-            const uint64_t k = t - poff[lo];
-            uint64_t y = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)k)) * 0.5);
+            const uint64_t k = t - wpoff[lo];
+            uint64_t y = (uint64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
             while (y * (y - 1) / 2 > k) --y;
             while ((y + 1) * y / 2 <= k) ++y;
             const uint64_t x = k - y * (y - 1) / 2;
             const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
-            want = B32R4 ? pair_found_here_b32r4(la, lb, n32, sig, M, F, offs, R, i, j)
-                         : pair_found_here(la, lb, n32, sig, M, b, r, F, offs, R, i, j);
+            want = pair_first_here(la, lb, n32, b, C, i, j);
         }
-        const unsigned long long slot = block_slot(count, want, &lcount, &gbase);
+        const unsigned long long slot = block_slot(count, want, &lcount, &gbase);  // (synchronises the block)
         if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
     }
 }
@@ -577,7 +699,7 @@ static LshLayout lsh_layout(int64_t n, int32_t b, int64_t cap) {
     auto take = [&](size_t bytes) { size_t o = off; off += align_up(std::max<size_t>(bytes, 1), 256); return o; };
     L.rec_a = take(sizeof(uint64_t) * recs);
     L.rec_b = take(sizeof(uint64_t) * recs);
-    L.fp = take((size_t)recs);
+    L.fp = take(sizeof(uint32_t) * (size_t)n * class_stride(b));  // class ids C[n][b], rows padded
     const int64_t T = runs_tiles(recs);
     L.runs = take(sizeof(uint64_t) * (size_t)T * kRunsCap);
     L.poff = take(sizeof(uint64_t) * (size_t)(2 * long_cap(recs) + 3 * T));
@@ -612,7 +734,7 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     const int64_t recs = n * b;
     uint64_t *rec_a = reinterpret_cast<uint64_t *>(ws + L.rec_a);
     uint64_t *rec_b = reinterpret_cast<uint64_t *>(ws + L.rec_b);
-    uint8_t *F = reinterpret_cast<uint8_t *>(ws + L.fp);
+    uint32_t *C = reinterpret_cast<uint32_t *>(ws + L.fp);
     unsigned long long *count = reinterpret_cast<unsigned long long *>(ws + L.misc);
     void *rscratch = ws + L.radix;
     const size_t rscratch_bytes = radix_scratch_bytes(std::max<int64_t>(recs, cap));
@@ -632,9 +754,9 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
         ProfScope prof("lsh_keys_kernel", st);
         const unsigned g = (unsigned)ceil_div(n, kKeysTileSeqs);
         if (r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0)
-            lsh_keys_kernel<true><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, F);
+            lsh_keys_kernel<true><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, C);
         else
-            lsh_keys_kernel<false><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, F);
+            lsh_keys_kernel<false><<<g, kKeysThreads, lds, st>>>(sig, n, M, b, r, offs, R, keep, band_in_key, rec_a, C);
     }
     SQ_LAUNCHED("lsh_keys_kernel");
     uint64_t *sorted = nullptr;
@@ -674,33 +796,36 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
         }
         SQ_LAUNCHED("lsh_compact_kernel");
     }
-    // 32 bands of 4 words, 16-byte aligned rows: the pair test with fused loads
-    const bool b32r4 = b == 32 && r == 4 && M % 2 == 0 && ((uintptr_t)sig & 15) == 0;
+    // exact classes inside the runs, then the emission of the short and the long runs
+    {
+        const unsigned g = (unsigned)((int64_t)device_cus() * 8);
+        {
+            // one thread per run: up to half the records start one
+            const unsigned gs = (unsigned)std::min<int64_t>(ceil_div(recs / 2 + 1, 256), (int64_t)device_cus() * 64);
+            ProfScope prof("lsh_class_small_kernel", st);
+            lsh_class_small_kernel<<<gs, 256, 0, st>>>(sorted, n, sig, M, b, r, offs, R, runs, counters, C);
+        }
+        SQ_LAUNCHED("lsh_class_small_kernel");
+        {
+            ProfScope prof("lsh_class_long_kernel", st);
+            lsh_class_long_kernel<<<g, 256, 0, st>>>(sorted, n, sig, M, b, r, offs, R, bruns, counters, C);
+        }
+        SQ_LAUNCHED("lsh_class_long_kernel");
+    }
+    uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
     {
         ProfScope prof("lsh_emit_small_kernel", st);
         const unsigned g = (unsigned)((int64_t)device_cus() * 8);
-        uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
-        if (b32r4)
-            lsh_emit_small_kernel<true><<<g, kEmitThreads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, runs,
-                                                                    counters, pk, cap, count);
-        else
-            lsh_emit_small_kernel<false><<<g, kEmitThreads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, runs,
-                                                                     counters, pk, cap, count);
+        lsh_emit_small_kernel<<<g, kEmitThreads, 0, st>>>(sorted, n, b, C, nb, runs, counters, pk, cap, count);
     }
     SQ_LAUNCHED("lsh_emit_small_kernel");
     {
         const int emit_threads = knob(SUBQUAD_KNOB_EMIT_THREADS);
-        ProfScope prof("lsh_emit_kernel", st);
+        ProfScope prof("lsh_emit_long_kernel", st);
         const unsigned g = (unsigned)((int64_t)device_cus() * 16);
-        uint64_t *pk = reinterpret_cast<uint64_t *>(ws + L.pk_a);
-        if (b32r4)
-            lsh_emit_kernel<true><<<g, emit_threads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff,
-                                                              counters, pk, cap, count);
-        else
-            lsh_emit_kernel<false><<<g, emit_threads, 0, st>>>(sorted, n, sig, M, b, r, F, offs, R, nb, bruns, bpoff,
-                                                               counters, pk, cap, count);
+        lsh_emit_long_kernel<<<g, emit_threads, 0, st>>>(sorted, n, b, C, nb, bruns, bpoff, counters, pk, cap, count);
     }
-    SQ_LAUNCHED("lsh_emit_kernel");
+    SQ_LAUNCHED("lsh_emit_long_kernel");
     return SUBQUAD_OK;
 }
 
