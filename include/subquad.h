@@ -59,7 +59,7 @@ const char *subquad_version(void);
  */
 enum subquad_knob {
     SUBQUAD_KNOB_MINHASH_BLOCKS_PER_CU = 0,  /* persistent MinHash blocks per CU (default 2) */
-    SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU = 1,    /* persistent alignment blocks per CU (default 4) */
+    SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU = 1,    /* alignment blocks per CU, at most the resident ones (16) */
     SUBQUAD_KNOB_GATE_GROUPS_PER_CU = 2,     /* 16-lane pair groups per CU (default 64)       */
     SUBQUAD_KNOB_EMIT_THREADS = 3,           /* LSH long-run emission block size (512)         */
     SUBQUAD_KNOB_COUNT = 4
@@ -203,7 +203,7 @@ int subquad_align_batch_dev(const uint8_t *seqs, const int32_t *lens, int64_t n,
  * call is made.
  *   Arguments and results as subquad_align_batch.  P must be at most
  *   SUBQUAD_ALIGN_NOALLOC_MAX_PAIRS, else SUBQUAD_ERR_ARG and nothing is enqueued.
- *   The array (17 MiB) is held by every GPU the library runs on until the process ends.
+ *   The array (33 MiB) is held by every GPU the library runs on until the process ends.
  *   All calls on one GPU share it: calls that overlap in time on one GPU (other streams,
  *   other threads) race and give wrong scores; calls ordered on one stream are safe.
  *   Nothing in the array needs to start at zero, so a call never reads what an earlier

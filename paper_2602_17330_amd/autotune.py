@@ -18,7 +18,7 @@ from ._lib import KNOBS, check, lib
 
 CANDIDATES = {
     "minhash_blocks_per_cu": [1, 2],
-    "align_blocks_per_cu": [2, 4, 8, 16],
+    "align_blocks_per_cu": [4, 8, 16],
     "gate_groups_per_cu": [16, 32, 64, 128, 256],
     "emit_threads": [256, 512, 1024],
 }

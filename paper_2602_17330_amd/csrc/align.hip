@@ -27,7 +27,7 @@
 
 namespace subquad {
 
-constexpr int kAlignThreads = 512;
+constexpr int kAlignThreads = 256;
 constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..64)
 constexpr int kMaskCode = 20;          // rows past the shorter sequence's end
 constexpr int kMaskScore = -4096;
@@ -95,8 +95,34 @@ __global__ __launch_bounds__(kAlignKeyBins) void align_bins_kernel(const uint64_
     bin_end[k] = (uint32_t)lo;
 }
 
+// Per sorted position: the pair's rows and lengths with the shorter sequence first,
+// meta = (row a, row b, la | lb << 8 | swapped << 16, p), or z = ~0 for a pair with an
+// index out of range.  One gather pass, so that the alignment kernel reads one coalesced
+// record per pair instead of a chain of dependent loads.
+constexpr uint32_t kMetaBad = 0xFFFFFFFFu;
+__global__ __launch_bounds__(256) void align_meta_kernel(const uint64_t *__restrict__ srec,
+                                                         const int32_t *__restrict__ pairs,
+                                                         const int32_t *__restrict__ lens, int64_t n, int32_t stride,
+                                                         int64_t cap, const int64_t *__restrict__ P_dev,
+                                                         uint4 *__restrict__ meta) {
+    const int64_t P = align_count(cap, P_dev);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = (uint32_t)srec[q];
+        const int32_t i = pairs[2 * (int64_t)p], j = pairs[2 * (int64_t)p + 1];
+        uint4 m = make_uint4(0u, 0u, kMetaBad, p);
+        if (i >= 0 && j >= 0 && i < n && j < n) {
+            const int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
+            const bool swap = li > lj;
+            m.x = (uint32_t)(swap ? j : i);
+            m.y = (uint32_t)(swap ? i : j);
+            m.z = (uint32_t)(swap ? lj : li) | (uint32_t)(swap ? li : lj) << 8 | (swap ? 1u << 16 : 0u);
+        }
+        meta[q] = m;
+    }
+}
+
 struct AlignLayout {
-    size_t ra, rb, bins, radix, total;
+    size_t ra, rb, bins, meta, radix, total;
 };
 
 static AlignLayout align_layout(int64_t P) {
@@ -106,6 +132,7 @@ static AlignLayout align_layout(int64_t P) {
     L.ra = take(sizeof(uint64_t) * P);
     L.rb = take(sizeof(uint64_t) * P);
     L.bins = take(sizeof(uint32_t) * kAlignKeyBins);
+    L.meta = take(sizeof(uint4) * P);
     L.radix = take(radix_scratch_bytes(P));
     L.total = off;
     return L;
@@ -187,6 +214,118 @@ __device__ __forceinline__ int sw_lane(const uint8_t *__restrict__ arow, int la,
     return best;
 }
 
+// Two pairs per lane in packed half precision: pair A in the low halves, pair B in the high
+// halves of every register, each cell update two packed adds and one three-way packed
+// maximum (v_pk_maximum3_f16) for E, F and H.  Every value the recurrence produces is an
+// integer in [-(gap_open + 128), bound] with bound = (largest substitution score) x ROWS;
+// the caller takes this path only when bound <= 2048, where half precision represents every
+// such integer exactly, so the scores are the int32 recurrence's bit for bit.  Rows past a
+// pair's shorter sequence and columns past its longer one read the mask score -2048, which
+// no diagonal can lift above the non-negative gap states (bound - 2048 <= 0).
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ half2_t max3h(half2_t a, half2_t b, half2_t c) {
+    half2_t r;
+    asm("v_pk_maximum3_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ half2_t as_h2(uint32_t w) { return __builtin_bit_cast(half2_t, w); }
+
+constexpr int kMaskCol = 20;   // column code past a pair's longer sequence (packed path)
+constexpr int kHalfMask = -2048;
+constexpr int kHalfBound = 2048;
+
+// Row-pair table offsets from a shorter sequence's words already in registers (bytes at
+// x >= la masked), as row_pair_codes.
+template <int ROWS>
+__device__ __forceinline__ void row_pair_codes_w(const uint32_t (&w)[(ROWS + 3) / 4], int la,
+                                                 uint32_t (&idx2)[ROWS / 2]) {
+#pragma unroll
+    for (int k = 0; k < ROWS / 2; ++k) {
+        const int x0 = 2 * k, x1 = 2 * k + 1;
+        const int b0 = (int)((w[x0 >> 2] >> (8 * (x0 & 3))) & 0xFFu);
+        const int b1 = (int)((w[x1 >> 2] >> (8 * (x1 & 3))) & 0xFFu);
+        const int c0 = x0 < la ? min(b0, 19) : kMaskCode;
+        const int c1 = x1 < la ? min(b1, 19) : kMaskCode;
+        idx2[k] = (uint32_t)(c0 * kCodes + c1);
+    }
+}
+
+constexpr int kPackedWords = 8;  // longer-sequence words held in registers (stride <= 32)
+
+// The two pairs' DP: shorter sequences' words aw, longer sequences' words bw (registers).
+template <int ROWS>
+__device__ __forceinline__ void sw_lane2(const uint32_t (&awA)[(ROWS + 3) / 4], int laA,
+                                         const uint32_t (&bwA0)[kPackedWords], int lbA,
+                                         const uint32_t (&awB)[(ROWS + 3) / 4], int laB,
+                                         const uint32_t (&bwB0)[kPackedWords], int lbB,
+                                         const uint32_t *__restrict__ S2, int go, int ge, int &outA, int &outB) {
+    uint32_t idxA[ROWS / 2], idxB[ROWS / 2];
+    row_pair_codes_w<ROWS>(awA, laA, idxA);
+    row_pair_codes_w<ROWS>(awB, laB, idxB);
+    uint32_t bwA[kPackedWords], bwB[kPackedWords];
+#pragma unroll
+    for (int k = 0; k < kPackedWords; ++k) {
+        bwA[k] = bwA0[k];
+        bwB[k] = bwB0[k];
+    }
+    const half2_t zero = {(_Float16)0, (_Float16)0};
+    const half2_t ngo = {(_Float16)(-go), (_Float16)(-go)}, nge = {(_Float16)(-ge), (_Float16)(-ge)};
+    half2_t Hp[ROWS], E[ROWS], HG[ROWS];
+#pragma unroll
+    for (int x = 0; x < ROWS; ++x) {
+        Hp[x] = zero;
+        E[x] = zero;
+        HG[x] = ngo;
+    }
+    half2_t best = zero;
+    const int lb = max(lbA, lbB);
+    for (int y0 = 0; y0 < lb; y0 += 4) {
+        const uint32_t curA = bwA[0], curB = bwB[0];
+#pragma unroll
+        for (int k = 0; k + 1 < kPackedWords; ++k) {  // the next word moves to the front
+            bwA[k] = bwA[k + 1];
+            bwB[k] = bwB[k + 1];
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+            const int y = y0 + k4;
+            if (y < lb) {
+                const int cA = y < lbA ? min((int)((curA >> (8 * k4)) & 0xFFu), 19) : kMaskCol;
+                const int cB = y < lbB ? min((int)((curB >> (8 * k4)) & 0xFFu), 19) : kMaskCol;
+                const uint32_t *colA = S2 + cA * (kCodes * kCodes);
+                const uint32_t *colB = S2 + cB * (kCodes * kCodes);
+                half2_t diag = zero, f = zero, hup_go = ngo;
+#pragma unroll
+                for (int k = 0; k < ROWS / 2; ++k) {
+                    const uint32_t wA = colA[idxA[k]], wB = colB[idxB[k]];
+                    // row 2k: (A's score, B's score); row 2k + 1 likewise
+                    const half2_t sc[2] = {as_h2(__builtin_amdgcn_perm(wB, wA, 0x05040100u)),
+                                           as_h2(__builtin_amdgcn_perm(wB, wA, 0x07060302u))};
+                    half2_t hh[2];
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int x = 2 * k + h2;
+                        const half2_t e = max3h(E[x] + nge, HG[x], zero);
+                        f = max3h(f + nge, hup_go, zero);
+                        const half2_t h = max3h(diag + sc[h2], e, f);
+                        diag = Hp[x];
+                        Hp[x] = h;
+                        E[x] = e;
+                        HG[x] = h + ngo;
+                        hup_go = HG[x];
+                        hh[h2] = h;
+                    }
+                    best = max3h(best, hh[0], hh[1]);
+                }
+            }
+        }
+    }
+    outA = (int)best.x;
+    outB = (int)best.y;
+}
+
 // Weighted global edit distance of one pair in one lane (the paper's Appendix F.3
 // recurrence with caller-given substitution costs and indel cost):
 //   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost(a_x, b_y)).
@@ -235,41 +374,114 @@ __device__ __forceinline__ int ed_lane(const uint8_t *__restrict__ arow, int la,
     return la == 0 ? lb * indel : res;
 }
 
-// Pairs of one rows bucket (shorter length in (ROWS-8, ROWS]), taken from the length-sorted
-// permutation: the bucket's range is read from the sort's end offsets on the device, so
-// the launch needs no host synchronisation.  Without a permutation (no workspace) every
-// pair is processed in input order with ROWS = the longest allowed row count.
+// Pairs of one rows bucket (shorter length in (ROWS-8, ROWS]), taken in the length order
+// (one metadata record per sorted position): the bucket's range is read from the sort's
+// end offsets on the device, so the launch needs no host synchronisation.
 template <int ROWS, int MODE>
 __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__restrict__ seqs,
                                                               const int32_t *__restrict__ lens, int64_t n,
                                                               int32_t stride, const int32_t *__restrict__ pairs,
-                                                              int64_t P, const uint64_t *__restrict__ perm,
+                                                              int64_t P, const uint4 *__restrict__ meta,
                                                               const uint32_t *__restrict__ bin_end,
                                                               const int8_t *__restrict__ subst, int go, int ge,
                                                               int32_t *__restrict__ scores) {
-    int64_t lo = 0, hi = P;
-    if (perm) {
-        constexpr int g = ROWS / 8;  // 1..8
-        lo = g > 1 ? (int64_t)bin_end[(g - 1) * 64 - 1] : 0;
-        hi = (int64_t)bin_end[g * 64 - 1];
-        if (hi > P) hi = P;
-    }
+    constexpr int g = ROWS / 8;  // 1..8
+    int64_t lo = g > 1 ? (int64_t)bin_end[(g - 1) * 64 - 1] : 0;
+    int64_t hi = (int64_t)bin_end[g * 64 - 1];
+    if (hi > P) hi = P;
     if (lo >= hi) return;  // whole grid
     if ((int64_t)blockIdx.x * (kAlignThreads / 64) >= ceil_div(hi - lo, 64)) return;  // whole block
-    __shared__ uint32_t S2[kS2Words];
+    __shared__ uint32_t S2[kS2Words + kCodes * kCodes];  // (+ the mask column of the packed path)
     __shared__ int8_t sub_sh[20 * 20];  // the 400 scores, loaded once (one load per thread)
-    int asym = 0;
+    __shared__ int smax;
+    if (threadIdx.x == 0) smax = -128;
+    __syncthreads();
+    int asym = 0, lmax = -128;
     for (int e = threadIdx.x; e < 20 * 20; e += blockDim.x) {
         const int8_t v = subst[e], vt = subst[(e % 20) * 20 + e / 20];
         sub_sh[e] = v;
         asym |= v != vt;
+        lmax = max(lmax, (int)v);
     }
+    atomicMax(&smax, lmax);
     // A symmetric matrix (BLOSUM, PAM) needs one pass.  An asymmetric one takes a second pass
     // over the block's pairs: the first aligns the pairs kept in (i, j) order, the second
     // those whose operands were swapped (the longer i runs across the columns), with the
     // table of the transposed matrix, since S(a_x, b_y) then reads S(col, row).
     asym = __syncthreads_or(asym);
     const int lane = threadIdx.x & 63;
+    // Two pairs per lane in packed half precision when every score of the bucket is an
+    // integer half precision holds exactly (symmetric matrix, ROWS <= 32 for the registers).
+    if (MODE == 0 && !asym && ROWS <= 32 && stride <= 4 * kPackedWords && max(smax, 0) * ROWS <= kHalfBound) {
+        for (int e = threadIdx.x; e < kS2Words + kCodes * kCodes; e += blockDim.x) {
+            const int c = e / (kCodes * kCodes);
+            const int rem = e - c * (kCodes * kCodes);
+            const int a0 = rem / kCodes, a1 = rem - a0 * kCodes;
+            const int s0 = (a0 < 20 && c < 20) ? (int)sub_sh[a0 * 20 + c] : kHalfMask;
+            const int s1 = (a1 < 20 && c < 20) ? (int)sub_sh[a1 * 20 + c] : kHalfMask;
+            const half2_t v = {(_Float16)s0, (_Float16)s1};
+            S2[e] = __builtin_bit_cast(uint32_t, v);
+        }
+        __syncthreads();
+        const int64_t nw2 = ceil_div(hi - lo, 128);
+        const int64_t wave0h = (int64_t)blockIdx.x * (kAlignThreads / 64) + (threadIdx.x >> 6);
+        const int64_t wsteph = (int64_t)gridDim.x * (kAlignThreads / 64);
+        constexpr int NA = (ROWS + 3) / 4;
+        const int D = stride >> 2;  // words per row (<= kPackedWords here)
+        // lane l takes sorted positions 2l and 2l + 1 of its wave's 128 (neighbours in the
+        // length order, so the two pairs' loops have nearly the same trip counts)
+        auto meta_at = [&](int64_t wv, int u) {
+            const int64_t idx = lo + wv * 128 + 2 * lane + u;
+            return (wv < nw2 && idx < hi) ? meta[idx] : make_uint4(0u, 0u, kMetaBad, 0u);
+        };
+        // the rows' words (a pair out of range reads row 0; its result is not stored)
+        auto rows_for = [&](const uint4 (&m)[2], uint32_t (&aw)[2][NA], uint32_t (&bw)[2][kPackedWords]) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const bool ok = m[u].z != kMetaBad;
+                const uint32_t *ra = reinterpret_cast<const uint32_t *>(seqs + (ok ? (int64_t)m[u].x : 0) * stride);
+                const uint32_t *rb = reinterpret_cast<const uint32_t *>(seqs + (ok ? (int64_t)m[u].y : 0) * stride);
+#pragma unroll
+                for (int w = 0; w < NA; ++w) aw[u][w] = ra[min(w, D - 1)];
+#pragma unroll
+                for (int w = 0; w < kPackedWords; ++w) bw[u][w] = w < D ? rb[w] : 0u;
+            }
+        };
+        // software pipeline: the next iteration's rows and the one after's records are loaded
+        // while this one computes
+        uint4 mc[2] = {meta_at(wave0h, 0), meta_at(wave0h, 1)};
+        uint4 mn[2] = {meta_at(wave0h + wsteph, 0), meta_at(wave0h + wsteph, 1)};
+        uint32_t ac[2][NA], bc[2][kPackedWords];
+        rows_for(mc, ac, bc);
+        for (int64_t wv = wave0h; wv < nw2; wv += wsteph) {
+            uint32_t an[2][NA], bn[2][kPackedWords];
+            rows_for(mn, an, bn);
+            const uint4 mnn[2] = {meta_at(wv + 2 * wsteph, 0), meta_at(wv + 2 * wsteph, 1)};
+            const bool ok0 = mc[0].z != kMetaBad, ok1 = mc[1].z != kMetaBad;
+            // a pair with an index out of range scores -1 (positions past the bucket carry no pair)
+            const int64_t i0 = lo + wv * 128 + 2 * lane;
+            if (!ok0 && i0 < hi) scores[mc[0].w] = -1;
+            if (!ok1 && i0 + 1 < hi) scores[mc[1].w] = -1;
+            if (ok0 || ok1) {
+                const int laA = ok0 ? min((int)(mc[0].z & 0xFFu), ROWS) : 0, lbA = ok0 ? (int)((mc[0].z >> 8) & 0xFFu) : 0;
+                const int laB = ok1 ? min((int)(mc[1].z & 0xFFu), ROWS) : 0, lbB = ok1 ? (int)((mc[1].z >> 8) & 0xFFu) : 0;
+                int sa = 0, sb = 0;
+                sw_lane2<ROWS>(ac[0], laA, bc[0], lbA, ac[1], laB, bc[1], lbB, S2, go, ge, sa, sb);
+                if (ok0) scores[mc[0].w] = sa;
+                if (ok1) scores[mc[1].w] = sb;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                mc[u] = mn[u];
+                mn[u] = mnn[u];
+#pragma unroll
+                for (int w = 0; w < NA; ++w) ac[u][w] = an[u][w];
+#pragma unroll
+                for (int w = 0; w < kPackedWords; ++w) bc[u][w] = bn[u][w];
+            }
+        }
+        return;
+    }
     const int64_t nw = ceil_div(hi - lo, 64);
     const int64_t wave0 = (int64_t)blockIdx.x * (kAlignThreads / 64) + (threadIdx.x >> 6);
     const int64_t wstep = (int64_t)gridDim.x * (kAlignThreads / 64);
@@ -293,28 +505,19 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
         __syncthreads();
         for (int64_t wv = wave0; wv < nw; wv += wstep) {
             const int64_t idx = lo + wv * 64 + lane;
-            bool valid = idx < hi;
-            int64_t p = 0;
-            if (valid) {
-                p = perm ? (int64_t)(uint32_t)perm[idx] : idx;
-                valid = p < P;
-            }
-            if (valid && !pair_ok(pairs, n, p)) {
-                valid = false;
+            if (idx >= hi) continue;
+            const uint4 m = meta[idx];
+            const int64_t p = m.w;
+            if (m.z == kMetaBad) {
                 if (pass == 0) scores[p] = -1;
+                continue;
             }
-            if (valid) {
-                int64_t i = pairs[2 * p], j = pairs[2 * p + 1];
-                int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
-                const bool swap = li > lj;
-                if (asym && swap != (pass == 1)) continue;
-                const uint8_t *arow, *brow;
-                int la, lb;
-                if (!swap) { arow = seqs + i * stride; la = li; brow = seqs + j * stride; lb = lj; }
-                else { arow = seqs + j * stride; la = lj; brow = seqs + i * stride; lb = li; }
-                if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge, (stride >> 2) - 1);
-                else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, (stride >> 2) - 1);
-            }
+            const bool swap = (m.z >> 16) & 1u;
+            if (asym && swap != (pass == 1)) continue;
+            const uint8_t *arow = seqs + (int64_t)m.x * stride, *brow = seqs + (int64_t)m.y * stride;
+            const int la = (int)(m.z & 0xFFu), lb = (int)((m.z >> 8) & 0xFFu);
+            if (MODE == 0) scores[p] = sw_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, ge, (stride >> 2) - 1);
+            else scores[p] = ed_lane<ROWS>(arow, min(la, ROWS), brow, lb, S2, go, (stride >> 2) - 1);
         }
     }
 }
@@ -374,24 +577,30 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     if (rc != SUBQUAD_OK) return rc;
     align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, P_dev, hist);
     SQ_LAUNCHED("align_bins_kernel");
-    uint64_t *perm = sorted;  // the pair index is the low word of each sorted record
+    uint4 *meta = reinterpret_cast<uint4 *>(base + L.meta);
+    align_meta_kernel<<<(unsigned)blocks, 256, 0, st>>>(sorted, pairs, lens, n, stride, P, P_dev, meta);
+    SQ_LAUNCHED("align_meta_kernel");
     const int64_t waves = ceil_div(P, 64);
-    const int64_t ablocks = std::min<int64_t>(ceil_div(waves, kAlignThreads / 64),
-                                              (int64_t)device_cus() * knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU));
+    // persistent blocks: no more than the chip holds at once for the bucket's kernel (a second
+    // round of blocks would leave a tail), and no more than the knob asks for
+    auto ablocks = [&](const void *kernel) {
+        const int per_cu = std::min(knob(SUBQUAD_KNOB_ALIGN_BLOCKS_PER_CU), resident_blocks_per_cu(kernel));
+        return (unsigned)std::min<int64_t>(ceil_div(waves, kAlignThreads / 64), (int64_t)device_cus() * per_cu);
+    };
     const uint32_t *bin_end = hist;
     if (mode == 0) {
         ProfScope prof("align_kernel", st);
 #define SQ_ROWS(R)                                                                                             \
-    align_kernel<R, 0><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, \
-                                                                    subst, go, ge, scores);
+    align_kernel<R, 0><<<ablocks((const void *)align_kernel<R, 0>), kAlignThreads, 0, st>>>(                   \
+        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores);
         SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
         if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
 #undef SQ_ROWS
     } else {
         ProfScope prof("edit_kernel", st);
 #define SQ_ROWS(R)                                                                                             \
-    align_kernel<R, 1><<<(unsigned)ablocks, kAlignThreads, 0, st>>>(seqs, lens, n, stride, pairs, P, perm, bin_end, \
-                                                                    subst, go, ge, scores);
+    align_kernel<R, 1><<<ablocks((const void *)align_kernel<R, 1>), kAlignThreads, 0, st>>>(                   \
+        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores);
         SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
         if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
 #undef SQ_ROWS
@@ -467,7 +676,7 @@ extern "C" int subquad_align_batch_dev(const uint8_t *seqs, const int32_t *lens,
 // array's name is only a stand-in, so its device address is looked up once per device
 // (hipGetSymbolAddress, with that device current) and only that address reaches kernels.
 constexpr int64_t kNoAllocMaxPairs = SUBQUAD_ALIGN_NOALLOC_MAX_PAIRS;
-constexpr size_t kNoAllocScratchBytes = size_t(17) << 20;  // >= align_layout(kNoAllocMaxPairs).total
+constexpr size_t kNoAllocScratchBytes = size_t(33) << 20;  // >= align_layout(kNoAllocMaxPairs).total
 static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
 
 static int noalloc_scratch(uint32_t **out) {

@@ -75,7 +75,7 @@ __global__ void check_seqs_kernel(const uint8_t *__restrict__ seqs, const int32_
 }
 
 static std::atomic<int> g_knobs[SUBQUAD_KNOB_COUNT] = {};
-static const int kKnobDefault[SUBQUAD_KNOB_COUNT] = {2, 4, 64, 512};
+static const int kKnobDefault[SUBQUAD_KNOB_COUNT] = {2, 16, 64, 512};
 
 int knob(int which) {
     int v = g_knobs[which].load(std::memory_order_relaxed);

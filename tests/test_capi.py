@@ -122,7 +122,7 @@ def test_binding_rejects_host_tensors():
 
 def test_knobs(L):
     # the defaults the header documents
-    assert [L.subquad_get_knob(k) for k in range(4)] == [2, 4, 64, 512]
+    assert [L.subquad_get_knob(k) for k in range(4)] == [2, 16, 64, 512]
     assert L.subquad_set_knob(2, 128) == 0 and L.subquad_get_knob(2) == 128
     assert L.subquad_set_knob(2, 0) == 0 and L.subquad_get_knob(2) == 64
     assert L.subquad_set_knob(3, 100) == 1            # not a multiple of 64
