@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
     ap.add_argument("--no-proto", action="store_true", help="skip the prototype-loss measurement")
     ap.add_argument("--no-rmt", action="store_true", help="skip the RMT edge-threshold measurement")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the 100k-sequence candidate statistics and steady-state GCUPS")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replayed step")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run N elementwise copies of 1 GiB (y = x * 1 over 2^28 float32: 1 GiB read, "
@@ -112,6 +114,42 @@ def time_region(torch, fn, steps, warmup):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
+
+
+def config2_leg(torch, sq, steps, warmup):
+    """The 100,000-sequence Zipf repertoire (lengths 8-25, M = 128, 32 x 4 bands): candidates
+    per query (every candidate pair counts for both its sequences) and steady-state
+    Smith-Waterman GCUPS on all its candidate pairs, and on the all-pairs block of its first
+    20,000 sequences (199,990,000 pairs), kernels alone (length sort included)."""
+    import synth
+    from paper_2602_17330_amd import api
+    rep = synth.zipf100k()
+    S = api.to_device(synth.load_blosum62())
+    seqs, lens = api.to_device(rep.seqs), api.to_device(rep.lens)
+    sig = sq.minhash(seqs, lens, 128)
+    pairs, _ = sq.lsh_candidates(sig, 32, 4)
+    P = int(pairs.shape[0])
+    deg = torch.bincount(pairs.long().reshape(-1), minlength=rep.n).double()
+    q = torch.quantile(deg, torch.tensor([0.5, 0.99], dtype=torch.float64, device=deg.device))
+    per_query = dict(mean=float(deg.mean()), p50=float(q[0]), p99=float(q[1]), max=float(deg.max()))
+    L = lens.long()
+
+    def sw_rate(pr):
+        cells = int((L[pr[:, 0].long()] * L[pr[:, 1].long()]).sum().item())
+        out = torch.empty(pr.shape[0], dtype=torch.int32, device="cuda")
+        ws = torch.empty(api.align_workspace_bytes(pr.shape[0]), dtype=torch.uint8, device="cuda")
+        t = time_region(torch, lambda: api.align(seqs, lens, pr, S, out=out, ws=ws), steps, warmup)
+        return dict(pairs=int(pr.shape[0]), cells=cells, ms=t * 1e3, gcups=cells / t / 1e9)
+
+    cand = sw_rate(pairs)
+    del pairs
+    iu = torch.triu_indices(20_000, 20_000, 1, device="cuda").t().to(torch.int32).contiguous()
+    block = sw_rate(iu)
+    del iu
+    torch.cuda.empty_cache()
+    return dict(workload="100,000 synthetic CDR3s (10,000 rank-Zipf(1.5) families), lengths 8-25, M=128, 32x4",
+                candidates=P, candidates_per_query=per_query, sw_candidates=cand,
+                sw_all_pairs_20k=block)
 
 
 def gate_2p20(torch, sq, steps, warmup):
@@ -664,6 +702,7 @@ def main():
     sw_gcups = kernels.get("align_kernel", {}).get("gcups")
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
+    cfg2 = None if a.no_config2 else config2_leg(torch, sq, max(3, min(a.steps, 5)), 1)
     proto = None if a.no_proto else proto_leg(torch, sq, rep, emb, max(3, min(a.steps, 5)), 1)
     rmt = None if a.no_rmt else rmt_leg(torch, sq, pipe)
     if a.calib_copy:
@@ -693,10 +732,13 @@ def main():
                                f"one fused pass)",
                    "n": n, "candidates": P, "cells": cells, "parallelism": "single GPU"},
         "sw_kernel_gcups": sw_gcups,
+        # the alignment stage alone (length sort, pair metadata, Smith-Waterman), from its events
+        "align_stage_gcups": cells / (stage_ms[STAGES.index("align")] / 1e3) / 1e9,
         "stage_ms": {s: float(m) for s, m in zip(STAGES, stage_ms)},
         "graph_ms_per_step": graph_ms,
         "graph_value": cells / (graph_ms / 1e3) / 1e9 if graph_ms else None,
         "gate_2p20": gate,
+        "zipf100k": cfg2,
         "proto_loss": proto,
         "rmt_threshold": rmt,
         "roofline": roof,

@@ -54,6 +54,54 @@ def test_gap_costs_and_lengths(S, go, ge):
     assert np.array_equal(got, sw_oracle(seqs, lens, pairs, S, go, ge))
 
 
+def _random_rows(rng, n, stride, lmin=1):
+    lens = rng.integers(lmin, stride + 1, n).astype(np.int32)
+    seqs = np.full((n, stride), synth.PAD, np.uint8)
+    for i in range(n):
+        seqs[i, : lens[i]] = rng.integers(0, 20, lens[i])
+    seqs[1::2, :] = seqs[0::2, :]  # related pairs: copies with a few edits
+    lens[1::2] = lens[0::2]
+    for i in range(1, n, 2):
+        for p in rng.choice(lens[i], min(lens[i], 3), replace=False):
+            seqs[i, p] = rng.integers(0, 20)
+    return seqs, lens
+
+
+@pytest.mark.parametrize("go,ge", [(10, 1), (1, 1), (5, 0), (0, 0), (1000, 1000), (11, 2)])
+def test_packed_path_gap_costs_and_lengths(S, go, ge):
+    """Rows of 32 bytes (the packed half-precision path: two pairs per lane), lengths 1-32 in
+    every bucket, odd pair counts (a lane with one pair), all gap settings, against the oracle."""
+    rng = np.random.default_rng(100 + go * 7 + ge)
+    n, stride = 500, 32
+    seqs, lens = _random_rows(rng, n, stride)
+    pairs = np.stack([rng.integers(0, n, 4001), rng.integers(0, n, 4001)], 1).astype(np.int32)
+    pairs = np.concatenate([pairs, np.stack([np.arange(0, n, 2), np.arange(1, n, 2)], 1)]).astype(np.int32)
+    say(f"align packed path go={go} ge={ge}")
+    got = _gpu(seqs, lens, pairs, S, go, ge)
+    assert np.array_equal(got, sw_oracle(seqs, lens, pairs, S, go, ge))
+
+
+@pytest.mark.parametrize("top", [64, 65, 127])
+def test_packed_path_score_bound(top):
+    """A symmetric matrix whose largest score times 32 rows is exactly the packed path's
+    bound (64: 2048, every value still exact in half precision) or above it (65, 127: the
+    block falls back to int32), on long self-similar pairs that reach the largest scores."""
+    rng = np.random.default_rng(top)
+    A = rng.integers(-20, 20, (20, 20))
+    A = np.triu(A) + np.triu(A, 1).T
+    np.fill_diagonal(A, top)
+    A = A.astype(np.int8)
+    n, stride = 300, 32
+    seqs, lens = _random_rows(rng, n, stride, lmin=20)
+    pairs = np.stack([rng.integers(0, n, 3000), rng.integers(0, n, 3000)], 1).astype(np.int32)
+    pairs = np.concatenate([pairs, np.stack([np.arange(n), np.arange(n)], 1)]).astype(np.int32)
+    say(f"align packed path bound top={top}")
+    got = _gpu(seqs, lens, pairs, A, 10, 1)
+    ref = sw_oracle(seqs, lens, pairs, A, 10, 1)
+    assert np.array_equal(got, ref)
+    assert ref.max() >= 20 * top  # the self pairs reach the large scores
+
+
 def test_self_pairs_and_self_scores(S):
     r = synth.tiny(seed=3, Lmin=3, Lmax=32)
     pairs = np.stack([np.arange(r.n), np.arange(r.n)], 1).astype(np.int32)
