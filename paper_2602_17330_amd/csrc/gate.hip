@@ -22,6 +22,10 @@
 
 namespace subquad {
 
+#ifndef SQ_GATE_RING
+#define SQ_GATE_RING 2
+#endif
+constexpr int kGateRing = SQ_GATE_RING;  // load slots of the first backward pass
 constexpr int kWeightStride = 8;  // floats per hidden unit of the LDS weight table
 constexpr int kGateMaxH = 256;
 
@@ -51,8 +55,8 @@ __global__ void gate_node_pack_kernel(const int32_t *__restrict__ self, const in
         node[k] = make_int4(self[k], lens[k], vgene[k], label ? label[k] : 0);
 }
 
-// The MLP's weights in LDS, kWeightStride floats per hidden unit (W1 row, b1, w2, two
-// spare), so that the gather kernels keep their registers for loads in flight.  The whole
+// The MLP's weights in LDS, kWeightStride floats per hidden unit (W1 row, b1, w2,
+// W1[.][c] w2, one spare), so that the gather kernels keep their registers for loads in flight.  The whole
 // block calls it.
 __device__ __forceinline__ void stage_weights(const GateIn &in, float *wsh) {
     for (int e = threadIdx.x; e < in.H; e += blockDim.x) {
@@ -63,7 +67,7 @@ __device__ __forceinline__ void stage_weights(const GateIn &in, float *wsh) {
         r[3] = in.W1[e * 4 + 3];
         r[4] = in.b1[e];
         r[5] = in.w2[e];
-        r[6] = 0.f;
+        r[6] = r[1] * r[5];  // W1[e][c] w2[e]: the unit's weight in the gradient by c
         r[7] = 0.f;
     }
     __syncthreads();
@@ -268,15 +272,34 @@ struct TrainOut {
 // recomputes the forward, accumulates e_i's gradient in registers over its row, and stores
 // per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
 // feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
+//
+// The gathers run ahead of the arithmetic through a ring of kGateBatch slots: slot u holds
+// the loads of one pair (e_j, j's node record, the alignment score and, when the pair starts
+// a new row, e_i and i's node record), and as soon as its pair is computed the slot is
+// refilled with the pair kGateBatch places further on.  Every gather, including the row of
+// the next i, is thus in flight while the pairs before it compute; the pair indices are
+// fetched one ring turn further ahead still.
+template <int NV>
+struct RingSlot {
+    int32_t p;  // pair number, -1: past the chunk
+    int32_t i;  // -1: an out-of-range pair
+    int4 nj, ni;  // node records of j and (new row only) of i
+    int32_t al;
+    float gf;   // upstream gradient (not TRAIN)
+    float4 ej[NV], ei[NV];  // ei: new row only
+};
+
 // The walk of gate_bwd_kernel over the chunk [q0, q1) of one lane group (NATURAL: the pairs
-// are in order of i, p = q); returns the group's sum of loss terms (TRAIN, lane 0).
-template <int NV, int UNITS, bool TRAIN, bool NATURAL>
+// are in order of i, p = q; SET: demb is written, not added to); returns the group's sum of
+// loss terms (TRAIN, lane 0).
+template <int NV, int UNITS, bool TRAIN, bool NATURAL, bool SET>
 __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *__restrict__ gfused,
                                                 const uint64_t *__restrict__ order_i, const float *wsh,
                                                 float4 *__restrict__ pack, float4 *__restrict__ feat,
                                                 float *__restrict__ demb, const TrainOut &tr, int64_t P, int64_t q0,
                                                 int64_t q1, int l, int d4, float b2, float4 (*stage)[2],
                                                 float *fstage) {
+    constexpr int R = kGateRing;
     double loss_acc = 0.0;
     if (q0 >= q1) return loss_acc;
     if (in.n == 0) {  // no rows: every pair is out of range
@@ -288,22 +311,41 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
         }
         return loss_acc;
     }
+    const int64_t n = in.n;
+    // the row of the record before the chunk: a first row equal to it started in another chunk
+    const int64_t key_before = q0 > 0 ? (int64_t)(order_i[q0 - 1] >> 32) : -1;
+    // e_i's gradient over its row is sum_p a_p e_j(p) - B e_i with a_p = cbar_p / (|e_i||e_j|)
+    // and B = sum_p cbar_p c_p / |e_i|^2: gi holds the first sum, bsum the scalar B, and the
+    // e_i term is applied once when the row is flushed.
     float4 ei[NV], gi[NV], old[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < NV; ++k) {
+        gi[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        old[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float bsum = 0.f;
+    int64_t cur_i = -1;
+    auto flush = [&](bool owned) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            gi[k].x = fmaf(-bsum, ei[k].x, gi[k].x);
+            gi[k].y = fmaf(-bsum, ei[k].y, gi[k].y);
+            gi[k].z = fmaf(-bsum, ei[k].z, gi[k].z);
+            gi[k].w = fmaf(-bsum, ei[k].w, gi[k].w);
+        }
+        bsum = 0.f;
+        flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, owned);
+    };
     float ni2 = 0.f;
     int4 ni = make_int4(0, 0, 0, 0);
-    int64_t cur_i = -1;
     bool started_here = false;
-    // The pair indices of the next batch are fetched while the current one is computed:
-    // pn = pair number, inx = i, jnx = j.  The loads are unconditional (indices past the
-    // chunk are clamped to its last pair, and such entries are dropped at use), so that no
-    // wait follows them.
-    uint32_t pn[kGateBatch];
-    int32_t inx[kGateBatch], jnx[kGateBatch];
+    // indices of the next ring turn: pair number, i and j of walk positions qb .. qb + R - 1
+    // (clamped to the chunk's last pair, so that every load is unconditional)
+    uint32_t pn[R];
+    int32_t inx[R], jnx[R];
     auto fetch = [&](int64_t qb) {
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) {
+        for (int u = 0; u < R; ++u) {
             const int64_t qq = min(qb + u, q1 - 1);
             const uint32_t pp = NATURAL ? (uint32_t)qq : (uint32_t)order_i[qq];
             pn[u] = pp;
@@ -311,105 +353,126 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
             jnx[u] = in.pairs[2 * (int64_t)pp + 1];
         }
     };
+    int32_t last_i = -1;  // i of the last pair put in the ring (-1: none, or out of range)
+    RingSlot<NV> slot[R];
+    // Slot u takes the pair at walk position q (its indices in pn[u], inx[u], jnx[u]).  The
+    // loads of a live pair are unconditional; e_i and i's record are loaded when the pair's
+    // row differs from the previous pair's.
+    auto issue = [&](int u, int64_t q) {
+        RingSlot<NV> &s = slot[u];
+        const bool live = q < q1;
+        const int32_t ii = inx[u], jj = jnx[u];
+        const bool ok = live && ii >= 0 && jj >= 0 && ii < n && jj < n;
+        s.p = live ? (int32_t)pn[u] : -1;
+        s.i = ok ? ii : -1;
+        const int64_t js = ok ? jj : 0, ps = pn[u];
+        s.nj = in.node[js];
+        s.al = in.align[ps];
+        if (!TRAIN) s.gf = gfused[ps];
+        load_row_flat<NV>(in.emb, js, d4, l, s.ej);
+        if (ok && ii != last_i) {
+            s.ni = in.node[ii];
+            load_row_flat<NV>(in.emb, ii, d4, l, s.ei);
+        }
+        if (live) last_i = ok ? ii : -1;
+    };
     fetch(q0);
-    for (int64_t q = q0; q < q1; q += kGateBatch) {
-        int64_t pb[kGateBatch], ib[kGateBatch], jb[kGateBatch];
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) {
-            const bool live = q + u < q1;
-            pb[u] = live ? (int64_t)pn[u] : -1;
-            ib[u] = live ? inx[u] : -1;
-            jb[u] = live ? jnx[u] : -1;
-        }
-        PairLoad<NV> pl[kGateBatch];
-        float gfb[kGateBatch];
+    for (int u = 0; u < R; ++u) issue(u, q0 + u);
+    fetch(q0 + R);
+    for (int64_t q = q0; q < q1; q += R) {
+        int32_t pb[R];
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) {
-            load_pair<NV, true>(in, pb[u], ib[u], jb[u], d4, l, pl[u]);
-            if (!TRAIN) gfb[u] = pl[u].i >= 0 ? gfused[pb[u]] : 0.f;
-        }
-        if (q + kGateBatch < q1) fetch(q + kGateBatch);
+        for (int u = 0; u < R; ++u) {
+            const RingSlot<NV> &s = slot[u];
+            pb[u] = s.p;
+            if (s.p >= 0) {
+                if (s.i < 0) {  // out-of-range pair: skipped
+                    if (l == 0) {
+                        stage[u][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        stage[u][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        fstage[u] = __builtin_nanf("");
+                    }
+                } else {
+                    const int64_t i = s.i;
+                    if (i != cur_i) {
+                        if (cur_i >= 0 && demb) flush(started_here);
+                        // the row starts inside this chunk unless the record before the chunk is in it too
+                        started_here = cur_i >= 0 || q0 == 0 || key_before != i;
+                        cur_i = i;
+                        if (demb && !SET) load_grad_row<NV>(demb, i, d4, l, old);
+                        ni = s.ni;
+                        float a = 0.f;
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) {
-            if (pb[u] < 0) break;
-            const int64_t p = pb[u];
-            if (pl[u].i < 0) {  // out-of-range pair: skipped
-                if (l == 0) {
-                    stage[u][0] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    stage[u][1] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    fstage[u] = __builtin_nanf("");
-                }
-                continue;
-            }
-            const int64_t i = pl[u].i;
-            if (i != cur_i) {
-                if (cur_i >= 0 && demb) flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here);
-                cur_i = i;
-                // The row starts inside this chunk unless the record before the chunk is in it too.
-                started_here = q0 == 0 || (int64_t)(order_i[q0 - 1] >> 32) != i;
-                if (demb) {
-                    if (tr.set_demb) {  // written, not added to: the row's old value counts as zero
+                        for (int k = 0; k < NV; ++k) {
+                            ei[k] = s.ei[k];
+                            a += dot4(ei[k], ei[k]);
+                        }
+                        ni2 = group_sum(a);
+                    }
+                    PairLoad<NV> pl;
+                    pl.i = s.i;
+                    pl.nj = s.nj;
+                    pl.al = s.al;
 #pragma unroll
-                        for (int k = 0; k < NV; ++k) old[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    for (int k = 0; k < NV; ++k) pl.ej[k] = s.ej[k];
+                    const PairFeat ft = pair_features<NV>(pl, ni);
+                    PairState<UNITS> st;
+                    pair_forward<NV, UNITS>(ei, ni2, pl, ft, wsh, l, b2, st);
+                    float gf;
+                    if (TRAIN) {
+                        const float f = fused_value(st, ft);
+                        float lp;
+                        if (ft.same_label) {
+                            const float e = 1.f - f;
+                            lp = e * e;
+                            gf = -2.f * e * tr.inv_P;
+                        } else {
+                            const float h = fmaxf(f - tr.margin, 0.f);
+                            lp = h * h;
+                            gf = 2.f * h * tr.inv_P;
+                        }
+                        if (l == 0) {
+                            loss_acc += (double)lp;
+                            fstage[u] = f;
+                        }
                     } else {
-                        load_grad_row<NV>(demb, i, d4, l, old);
+                        gf = s.gf;
+                    }
+                    const float ubar = gf * (ft.s - st.c) * st.g * st.gm;
+                    float xc = 0.f;
+#pragma unroll
+                    for (int k = 0; k < UNITS; ++k) {
+                        const float *r = wsh + (l + kGroup * k) * kWeightStride;
+                        xc += st.z[k] > 0.f ? r[6] : 0.f;
+                    }
+                    const float cbar = gf * st.gm + ubar * group_sum(xc);
+                    const float inv = st.inv;
+                    if (l == 0) {
+                        stage[u][0] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
+                        stage[u][1] = make_float4(ft.s, st.c, ft.x2, ft.x3);
+                    }
+                    if (demb && st.ok) {
+                        const float a = cbar * inv;
+                        bsum = fmaf(cbar * st.c, rcp_fast(ni2), bsum);
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) {
+                            gi[k].x = fmaf(a, pl.ej[k].x, gi[k].x);
+                            gi[k].y = fmaf(a, pl.ej[k].y, gi[k].y);
+                            gi[k].z = fmaf(a, pl.ej[k].z, gi[k].z);
+                            gi[k].w = fmaf(a, pl.ej[k].w, gi[k].w);
+                        }
                     }
                 }
-                ni = in.node[i];
-                load_row_norm<NV>(in, i, d4, l, ei, ni2);
             }
-            const PairFeat ft = pair_features<NV>(pl[u], ni);
-            PairState<UNITS> st;
-            pair_forward<NV, UNITS>(ei, ni2, pl[u], ft, wsh, l, b2, st);
-            float gf;
-            if (TRAIN) {
-                const float f = fused_value(st, ft);
-                float lp;
-                if (ft.same_label) {
-                    const float e = 1.f - f;
-                    lp = e * e;
-                    gf = -2.f * e * tr.inv_P;
-                } else {
-                    const float h = fmaxf(f - tr.margin, 0.f);
-                    lp = h * h;
-                    gf = 2.f * h * tr.inv_P;
-                }
-                if (l == 0) {
-                    loss_acc += (double)lp;
-                    fstage[u] = f;
-                }
-            } else {
-                gf = gfb[u];
-            }
-            const float ubar = gf * (ft.s - st.c) * st.g * st.gm;
-            float xc = 0.f;
-#pragma unroll
-            for (int k = 0; k < UNITS; ++k) {
-                const float *r = wsh + (l + kGroup * k) * kWeightStride;
-                xc += st.z[k] > 0.f ? r[1] * r[5] : 0.f;
-            }
-            const float cbar = gf * st.gm + ubar * group_sum(xc);
-            const float inv = st.inv;
-            if (l == 0) {
-                stage[u][0] = make_float4(st.ok ? cbar : 0.f, st.c, inv, ubar);
-                stage[u][1] = make_float4(ft.s, st.c, ft.x2, ft.x3);
-            }
-            if (demb && st.ok) {
-                const float ci = st.c * rcp_fast(st.ni * st.ni);
-#pragma unroll
-                for (int k = 0; k < NV; ++k) {
-                    gi[k].x += cbar * (pl[u].ej[k].x * inv - ci * ei[k].x);
-                    gi[k].y += cbar * (pl[u].ej[k].y * inv - ci * ei[k].y);
-                    gi[k].z += cbar * (pl[u].ej[k].z * inv - ci * ei[k].z);
-                    gi[k].w += cbar * (pl[u].ej[k].w * inv - ci * ei[k].w);
-                }
-            }
+            issue(u, q + R + u);  // the slot takes the pair one ring turn ahead
         }
-        // the batch's per-pair records leave together: lane u stores pair u's (consecutive
+        if (q + 2 * R < q1) fetch(q + 2 * R);
+        // the turn's per-pair records leave together: lane u stores pair u's (consecutive
         // pairs give one contiguous store per array)
-        int64_t mine = -1;  // the pair this lane stores (lane u: pair u)
+        int32_t mine = -1;
 #pragma unroll
-        for (int u = 0; u < kGateBatch; ++u) mine = l == u ? pb[u] : mine;
+        for (int u = 0; u < R; ++u) mine = l == u ? pb[u] : mine;
         if (mine >= 0) {
             pack[mine] = stage[l][0];
             feat[mine] = stage[l][1];
@@ -418,14 +481,14 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
     }
     if (cur_i >= 0 && demb) {
         const bool ends_here = q1 == P || (int64_t)(order_i[q1] >> 32) != cur_i;
-        flush_row_pre<NV>(demb, cur_i, d4, l, gi, old, started_here && ends_here);
+        flush(started_here && ends_here);
     }
     return loss_acc;
 }
 
 // (Three waves per SIMD: the register budget is capped at 168 so that the TRAIN variant
 // keeps that occupancy.)
-template <int NV, int UNITS, bool TRAIN>
+template <int NV, int UNITS, bool TRAIN, bool SET>
 __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3))) void gate_bwd_kernel(
     GateIn in, const float *__restrict__ gfused, const uint64_t *__restrict__ order_nat,
     const uint64_t *__restrict__ order_sorted, const int64_t *__restrict__ unsorted, float4 *__restrict__ pack,
@@ -449,10 +512,10 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ float fstage[kGateThreads / kGroup][kGateBatch];
     const int g = threadIdx.x / kGroup;
     const double loss_acc =
-        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1, l, d4,
-                                                        b2, stage[g], fstage[g])
-                : gate_bwd_walk<NV, UNITS, TRAIN, false>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1, l,
-                                                         d4, b2, stage[g], fstage[g]);
+        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true, SET>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1,
+                                                             l, d4, b2, stage[g], fstage[g])
+                : gate_bwd_walk<NV, UNITS, TRAIN, false, SET>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1,
+                                                              l, d4, b2, stage[g], fstage[g]);
     if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
         __shared__ double red[kGateThreads];
         red[threadIdx.x] = loss_acc;
@@ -714,7 +777,8 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
 #define SQ_CASE(U)                                                                                                 \
     case U: {                                                                                                      \
         {                                                                                                          \
-            const int64_t blocks = gate_blocks(in.P, (const void *)gate_bwd_kernel<NV, U, TRAIN>);                 \
+            const auto kern = tr.set_demb ? gate_bwd_kernel<NV, U, TRAIN, true> : gate_bwd_kernel<NV, U, TRAIN, false>; \
+            const int64_t blocks = gate_blocks(in.P, (const void *)kern);                                          \
             if (lblocks) *lblocks = blocks;                                                                        \
             if (demb && tr.set_demb) {                                                                             \
                 const int64_t pblocks = std::min<int64_t>(ceil_div(in.P + 1, 256), gate_max_blocks() * 4);          \
@@ -725,8 +789,8 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
                 SQ_LAUNCHED("gate_set_rows_prep_kernel");                                                          \
             }                                                                                                      \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
-            gate_bwd_kernel<NV, U, TRAIN><<<(unsigned)blocks, kGateThreads, 0, st>>>(                                \
-                in, gf, o.order_nat, o.order_i, o.unsorted, pack, feat, demb, tr);                                \
+            kern<<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, o.order_nat, o.order_i, o.unsorted, pack, feat,  \
+                                                            demb, tr);                                             \
         }                                                                                                          \
         SQ_LAUNCHED("gate_bwd_kernel");                                                                            \
         {                                                                                                          \

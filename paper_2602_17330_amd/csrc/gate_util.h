@@ -165,6 +165,20 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     float inv_nu2 = 0.f;
     int64_t cur = -1;
     bool started_here = false;
+    // the row's gradient is sum_p a_p e_i(p) - B e_u (a_p = cbar_p inv_p, B = sum_p cbar_p c_p
+    // / |e_u|^2): acc holds the sum, bsum the scalar B, and the e_u term is applied at the flush
+    float bsum = 0.f;
+    auto flush = [&](bool owned) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            acc[k].x = fmaf(-bsum, eu[k].x, acc[k].x);
+            acc[k].y = fmaf(-bsum, eu[k].y, acc[k].y);
+            acc[k].z = fmaf(-bsum, eu[k].z, acc[k].z);
+            acc[k].w = fmaf(-bsum, eu[k].w, acc[k].w);
+        }
+        bsum = 0.f;
+        flush_row_pre<NV>(demb, cur, d4, l, acc, old, owned);
+    };
     // the next batch's order records are fetched while the current one is computed
     uint64_t nrec[kGateBatch];
 #pragma unroll
@@ -208,7 +222,7 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
             if (ub[t] < 0) break;
             const int64_t u = ub[t];
             if (u != cur) {
-                if (cur >= 0 && cur < n) flush_row_pre<NV>(demb, cur, d4, l, acc, old, started_here);
+                if (cur >= 0 && cur < n) flush(started_here);
                 cur = u;
                 // The row starts inside this chunk unless the record before the chunk is in it too.
                 started_here = q0 == 0 || (int64_t)(order_j[q0 - 1] >> 32) != u;
@@ -223,19 +237,20 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
                 }
             }
             if (ib[t] < 0) continue;
-            const float cu = pk[t].y * inv_nu2;
+            const float a = pk[t].x * pk[t].z;
+            bsum = fmaf(pk[t].x * pk[t].y, inv_nu2, bsum);
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                acc[k].x += pk[t].x * (ep[t][k].x * pk[t].z - cu * eu[k].x);
-                acc[k].y += pk[t].x * (ep[t][k].y * pk[t].z - cu * eu[k].y);
-                acc[k].z += pk[t].x * (ep[t][k].z * pk[t].z - cu * eu[k].z);
-                acc[k].w += pk[t].x * (ep[t][k].w * pk[t].z - cu * eu[k].w);
+                acc[k].x = fmaf(a, ep[t][k].x, acc[k].x);
+                acc[k].y = fmaf(a, ep[t][k].y, acc[k].y);
+                acc[k].z = fmaf(a, ep[t][k].z, acc[k].z);
+                acc[k].w = fmaf(a, ep[t][k].w, acc[k].w);
             }
         }
     }
     if (cur >= 0 && cur < n) {
         const bool ends_here = q1 == P || (int64_t)(order_j[q1] >> 32) != cur;
-        flush_row_pre<NV>(demb, cur, d4, l, acc, old, started_here && ends_here);
+        flush(started_here && ends_here);
     }
 }
 
