@@ -48,6 +48,13 @@ KERNEL_SOURCES = {
 }
 
 
+# Per-pair bytes of the gate's first backward pass with no reuse: the forward's two embedding
+# rows, pair, score and output (2 d 4 + 16 = 1,040 at d = 128) plus the i-side gradient row
+# (d 4 = 512).  Rows of a repeated i are served from registers and caches, so the rate this
+# gives can exceed what HBM moved.
+EFFECTIVE_BYTES_PER_PAIR = {"gate_bwd_kernel": 2 * 128 * 4 + 16 + 128 * 4}
+
+
 def kernel_source_sha(kernel):
     import hashlib
     h = hashlib.sha256()
@@ -83,6 +90,8 @@ def parse():
     ap.add_argument("--tune", action="store_true", help="autotune launch shapes before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true", help="skip the 2^20-pair gate measurement")
+    ap.add_argument("--gate-2p20-only", action="store_true",
+                    help="run only the 2^20-pair gate leg and print its JSON (for counter runs)")
     ap.add_argument("--no-proto", action="store_true", help="skip the prototype-loss measurement")
     ap.add_argument("--no-rmt", action="store_true", help="skip the RMT edge-threshold measurement")
     ap.add_argument("--no-config2", action="store_true",
@@ -103,6 +112,18 @@ def build_workload(name):
     rep = getattr(synth, name)()
     emb = synth.embeddings(rep.seqs, rep.lens, rep.params["d"])
     return rep, emb
+
+
+def calib_copy(torch, times):
+    """`times` launches of an elementwise copy of 2^28 float32 (1 GiB read, 1 GiB written): the
+    known-size kernel that scales the FETCH_SIZE and WRITE_SIZE counters to bytes."""
+    if not times:
+        return
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(times):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
 
 
 def time_region(torch, fn, steps, warmup):
@@ -582,6 +603,11 @@ def main():
     import synth
 
     sq.lib()  # fails loudly if the library is missing
+    if a.gate_2p20_only:
+        out = {"gate_2p20": gate_2p20(torch, sq, max(3, a.steps), a.warmup)}
+        calib_copy(torch, a.calib_copy)
+        print(json.dumps(out), flush=True)
+        return
     if a.workload == "batch64":
         return bench_batch64(a, torch, sq)
     log(f"building workload {a.workload}")
@@ -699,18 +725,21 @@ def main():
             "frac": kd["frac"], "traffic": traffic, "traffic_detail": traffic_detail, "kernel": dominant,
             "avg_launch_ms": kd["avg_launch_ms"],
             "alg_bytes_per_launch": kd.get("alg_bytes_per_launch", kd.get("alg_ops_per_launch"))}
+    if traffic:  # the bytes the counters saw, at the same launch time
+        roof["traffic_gbs"] = traffic / (kd["avg_launch_ms"] / 1e3) / 1e9
+        roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
+    eff = EFFECTIVE_BYTES_PER_PAIR.get(dominant)
+    if eff:  # the per-pair byte model of the gate (every gather counted, none served by a cache)
+        ach = eff * P / (kd["avg_launch_ms"] / 1e3) / 1e9
+        roof["effective"] = {"bytes_per_pair": eff, "pairs": P, "achieved": ach, "unit": "GB/s",
+                             "frac": ach / HBM_PEAK_GBS}
     sw_gcups = kernels.get("align_kernel", {}).get("gcups")
 
     gate = None if a.no_gate else gate_2p20(torch, sq, max(3, a.steps), a.warmup)
     cfg2 = None if a.no_config2 else config2_leg(torch, sq, max(3, min(a.steps, 5)), 1)
     proto = None if a.no_proto else proto_leg(torch, sq, rep, emb, max(3, min(a.steps, 5)), 1)
     rmt = None if a.no_rmt else rmt_leg(torch, sq, pipe)
-    if a.calib_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(a.calib_copy):
-            torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
+    calib_copy(torch, a.calib_copy)
     cpu = None if a.no_cpu_baseline else cpu_baseline(rep, emb, S, pipe, cfg)
 
     out = {
