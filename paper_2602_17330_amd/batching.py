@@ -22,12 +22,13 @@ def bytes_per_sequence(M: int, b: int, d: int, stride: int, pairs_per_seq: float
     """Device bytes one sequence brings to a batch on the hot path."""
     per_seq = (stride + 4 + 4 + 4 + 4          # sequence row, length, V-gene, family, self-score
                + 8 * M                          # signature row
-               + 2 * 8 * b + b                  # band records (two sort buffers) + fingerprints
+               + 2 * 8 * b                      # band records (two sort buffers)
+               + 4 * ((b + 3) // 4 * 4)         # exact class ids, rows padded to 16 bytes
                + 8 + 16                         # CSR row offset, gate node record
                + 2 * 4 * d)                     # embedding and its gradient
     per_pair = (8 + 2 * 8                        # pair, pair-sort keys (x2)
                 + 4 + 4 + 4                      # score, fused, upstream gradient
-                + 2 * 8                          # alignment length sort (x2)
+                + 2 * 8 + 16                     # alignment length sort (x2), metadata record
                 + 4 * 8 + 16 + 16)               # gate pair orders (x4), per-pair records (2 x 16)
     return per_seq + pairs_per_seq * per_pair
 
