@@ -26,7 +26,7 @@ namespace subquad {
 #define SQ_GATE_RING 2
 #endif
 constexpr int kGateRing = SQ_GATE_RING;  // load slots of the first backward pass
-constexpr int kWeightStride = 8;  // floats per hidden unit of the LDS weight table
+constexpr int kWeightStride = 8;  // floats per hidden unit of the LDS weight tables (two float4)
 constexpr int kGateMaxH = 256;
 
 struct GateIn {
@@ -55,22 +55,26 @@ __global__ void gate_node_pack_kernel(const int32_t *__restrict__ self, const in
         node[k] = make_int4(self[k], lens[k], vgene[k], label ? label[k] : 0);
 }
 
-// The MLP's weights in LDS, kWeightStride floats per hidden unit (W1 row, b1, w2,
-// W1[.][c] w2, one spare), so that the gather kernels keep their registers for loads in flight.  The whole
-// block calls it.
+// The MLP's weights in LDS, so that the gather kernels keep their registers for loads in
+// flight: two tables of one 16-byte word per hidden unit, A[u] = W1's row u and
+// B[u] = (b1[u], w2[u], W1[u][c] w2[u] (the unit's weight in the gradient by c), 0).  Lane l
+// of a pair group reads unit l + 16 k, so a group's 16 reads cover 256 contiguous bytes
+// (no bank conflicts; the groups of a wave read the same words).  The whole block calls it.
 __device__ __forceinline__ void stage_weights(const GateIn &in, float *wsh) {
+    float4 *A = reinterpret_cast<float4 *>(wsh), *B = A + kGateMaxH;
     for (int e = threadIdx.x; e < in.H; e += blockDim.x) {
-        float *r = wsh + e * kWeightStride;
-        r[0] = in.W1[e * 4 + 0];
-        r[1] = in.W1[e * 4 + 1];
-        r[2] = in.W1[e * 4 + 2];
-        r[3] = in.W1[e * 4 + 3];
-        r[4] = in.b1[e];
-        r[5] = in.w2[e];
-        r[6] = r[1] * r[5];  // W1[e][c] w2[e]: the unit's weight in the gradient by c
-        r[7] = 0.f;
+        const float w0 = in.W1[e * 4 + 0], w1 = in.W1[e * 4 + 1], w2v = in.w2[e];
+        A[e] = make_float4(w0, w1, in.W1[e * 4 + 2], in.W1[e * 4 + 3]);
+        B[e] = make_float4(in.b1[e], w2v, w1 * w2v, 0.f);
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ float4 weight_row(const float *wsh, int unit) {
+    return reinterpret_cast<const float4 *>(wsh)[unit];
+}
+__device__ __forceinline__ float4 weight_aux(const float *wsh, int unit) {
+    return reinterpret_cast<const float4 *>(wsh)[kGateMaxH + unit];
 }
 
 // One pair's inputs as loaded by a group, before any of them is used: the partner row e_j,
@@ -158,11 +162,10 @@ __device__ __forceinline__ void pair_forward(const float4 (&ei)[NV], float ni2, 
     float part = 0.f;
 #pragma unroll
     for (int k = 0; k < UNITS; ++k) {
-        const float *r = wsh + (l + kGroup * k) * kWeightStride;
-        const float4 w = *reinterpret_cast<const float4 *>(r);
+        const float4 w = weight_row(wsh, l + kGroup * k), aux = weight_aux(wsh, l + kGroup * k);
         const float wv[4] = {w.x, w.y, w.z, w.w};
-        st.z[k] = unit_preact(wv, r[4], ft.s, st.c, ft.x2, ft.x3);
-        part = fmaf(r[5], fmaxf(st.z[k], 0.f), part);
+        st.z[k] = unit_preact(wv, aux.x, ft.s, st.c, ft.x2, ft.x3);
+        part = fmaf(aux.y, fmaxf(st.z[k], 0.f), part);
     }
     st.u = group_sum(part) + b2;
     // g = sigmoid(u) and gm = 1 - g from one exponential of -|u| (no overflow, and gm
@@ -443,8 +446,7 @@ __device__ __forceinline__ double gate_bwd_walk(const GateIn &in, const float *_
                     float xc = 0.f;
 #pragma unroll
                     for (int k = 0; k < UNITS; ++k) {
-                        const float *r = wsh + (l + kGroup * k) * kWeightStride;
-                        xc += st.z[k] > 0.f ? r[6] : 0.f;
+                        xc += st.z[k] > 0.f ? weight_aux(wsh, l + kGroup * k).z : 0.f;
                     }
                     const float cbar = gf * st.gm + ubar * group_sum(xc);
                     const float inv = st.inv;
