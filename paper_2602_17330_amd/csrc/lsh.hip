@@ -55,7 +55,8 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
     const uint64_t *__restrict__ sig, int64_t n, int32_t M, int32_t b, int32_t r,
     const int64_t *__restrict__ offs, int64_t R, uint32_t keep, uint32_t band_in_key, uint64_t *__restrict__ rec,
     uint32_t *__restrict__ C) {
-    extern __shared__ uint32_t keyhi[];  // [b][64]
+    extern __shared__ uint32_t keyhi[];  // [b][kKeysTileSeqs + 1] (rows padded: a wave's writes, one band apart, hit
+                                         // different banks)
     const int64_t i0 = (int64_t)blockIdx.x * kKeysTileSeqs;
     const int items = kKeysTileSeqs * b;
     // kKeysUnroll items per thread at a time, so that their signature loads are in flight
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
             if (!tup[u]) continue;
             const int e = e0 + u * kKeysThreads + threadIdx.x;
             const int s = e / b, beta = e - s * b;
-            keyhi[beta * kKeysTileSeqs + s] = ((uint32_t)(h[u] >> 32) & keep) | (band_in_key ? (uint32_t)beta : 0u);
+            keyhi[beta * (kKeysTileSeqs + 1) + s] = ((uint32_t)(h[u] >> 32) & keep) | (band_in_key ? (uint32_t)beta : 0u);
             C[(i0 + s) * class_stride(b) + beta] = (uint32_t)beta * (uint32_t)n + (uint32_t)(i0 + s);  // own class
         }
     }
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kKeysThreads) void lsh_keys_kernel(
         int64_t i = i0 + s;
         if (i >= n) continue;
         uint64_t q = (uint64_t)beta * (uint64_t)n + (uint64_t)i;
-        rec[q] = ((uint64_t)keyhi[e] << 32) | q;
+        rec[q] = ((uint64_t)keyhi[beta * (kKeysTileSeqs + 1) + s] << 32) | q;
     }
 }
 
@@ -749,7 +750,14 @@ static int lsh_front(const uint64_t *sig, int64_t n, int32_t M, int32_t b, int32
     // the band (b <= 256) goes into the cleared bits when there are any: runs then compare
     // whole key words, with no division by n
     const uint32_t band_in_key = mix_bits <= 24 ? 1u : 0u;
-    const size_t lds = sizeof(uint32_t) * kKeysTileSeqs * b;  // at most 64 KiB (b <= 256)
+    const size_t lds = sizeof(uint32_t) * (kKeysTileSeqs + 1) * b;  // at most 65 KiB (b <= 256)
+    static bool lds_attr = false;  // above 64 KiB the kernels must allow it (once per process)
+    if (lds > 65536 && !lds_attr) {
+        const int most = (int)(sizeof(uint32_t) * (kKeysTileSeqs + 1) * 256);
+        SQ_HIP(hipFuncSetAttribute((const void *)lsh_keys_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, most));
+        SQ_HIP(hipFuncSetAttribute((const void *)lsh_keys_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, most));
+        lds_attr = true;
+    }
     {
         ProfScope prof("lsh_keys_kernel", st);
         const unsigned g = (unsigned)ceil_div(n, kKeysTileSeqs);
