@@ -503,8 +503,7 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     const int l = threadIdx.x & (kGroup - 1);
     const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
     const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(P, ngroups);
-    const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
+    const int64_t chunk = gate_chunk(P, ngroups);
     const int d4 = in.d >> 2;
     __shared__ __align__(16) float wsh[kGateMaxH * kWeightStride];
     stage_weights(in, wsh);
@@ -513,11 +512,14 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     __shared__ float4 stage[kGateThreads / kGroup][kGateBatch][2];
     __shared__ float fstage[kGateThreads / kGroup][kGateBatch];
     const int g = threadIdx.x / kGroup;
-    const double loss_acc =
-        natural ? gate_bwd_walk<NV, UNITS, TRAIN, true, SET>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1,
-                                                             l, d4, b2, stage[g], fstage[g])
-                : gate_bwd_walk<NV, UNITS, TRAIN, false, SET>(in, gfused, order_i, wsh, pack, feat, demb, tr, P, q0, q1,
-                                                              l, d4, b2, stage[g], fstage[g]);
+    double loss_acc = 0.0;
+    for (int64_t q0 = group * chunk; q0 < P; q0 += ngroups * chunk) {
+        const int64_t q1 = min(P, q0 + chunk);
+        loss_acc += natural ? gate_bwd_walk<NV, UNITS, TRAIN, true, SET>(in, gfused, order_i, wsh, pack, feat, demb, tr,
+                                                                         P, q0, q1, l, d4, b2, stage[g], fstage[g])
+                            : gate_bwd_walk<NV, UNITS, TRAIN, false, SET>(in, gfused, order_i, wsh, pack, feat, demb,
+                                                                          tr, P, q0, q1, l, d4, b2, stage[g], fstage[g]);
+    }
     if (TRAIN) {  // block sum of the loss terms (held by lane 0 of each group)
         __shared__ double red[kGateThreads];
         red[threadIdx.x] = loss_acc;
@@ -738,7 +740,7 @@ __global__ __launch_bounds__(256) void gate_set_rows_prep_kernel(const uint64_t 
                                                                  int64_t ngroups, int d4, float *__restrict__ demb) {
     const uint64_t *order_i = unsorted[0] == 0 ? order_nat : order_sorted;
     const int64_t P = live_count(cap, P_dev);
-    const int64_t chunk = ceil_div(P, ngroups);  // the first pass's chunk of pairs per lane group
+    const int64_t chunk = gate_chunk(P, ngroups);  // the first pass's chunk of pairs
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -813,10 +815,16 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
             return SUBQUAD_ERR_ARG;
     }
     if (demb) {
-        const int64_t blocks = gate_blocks(in.P, (const void *)gate_cos_bwd_j_kernel<NV>);
+        // one chunk per lane group unless the capacity needs several capped ones
+        auto kern = gate_cos_bwd_j_kernel<NV, false>;
+        int64_t blocks = gate_blocks(in.P, (const void *)kern);
+        if (in.P > blocks * (kGateThreads / kGroup) * kGateChunkMax) {
+            kern = gate_cos_bwd_j_kernel<NV, true>;
+            blocks = gate_blocks(in.P, (const void *)kern);
+        }
         ProfScope prof("gate_cos_bwd_j_kernel", st);
-        gate_cos_bwd_j_kernel<NV><<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, in.P_dev,
-                                                                             order_j, pack, demb);
+        kern<<<(unsigned)blocks, kGateThreads, 0, st>>>(in.emb, in.n, in.d, in.pairs, in.P, in.P_dev, order_j, pack,
+                                                         demb);
     }
     SQ_LAUNCHED("gate_cos_bwd_j_kernel");
     return SUBQUAD_OK;

@@ -38,6 +38,16 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
+// Pairs per chunk of a lane group: P split evenly over the groups, but at most
+// kGateChunkMax; a group then takes chunks g, g + ngroups, ... so that at any time all
+// groups work inside one window of ngroups x chunk consecutive pairs, whose partner rows
+// (one repertoire's, or a few) stay in the caches while it is walked.
+constexpr int64_t kGateChunkMax = 4096;
+__host__ __device__ inline int64_t gate_chunk(int64_t P, int64_t ngroups) {
+    const int64_t c = (P + ngroups - 1) / ngroups;
+    return c < 1 ? 1 : (c < kGateChunkMax ? c : kGateChunkMax);
+}
+
 // Pairs to process: `cap`, or the count a producer left in device memory (clamped to
 // [0, cap]) when `count_dev` is set, so that a launch sized for the capacity needs no host
 // synchronisation.
@@ -144,19 +154,12 @@ __device__ __forceinline__ void flush_row_pre(float *__restrict__ demb, int64_t 
 // Second pass of the cosine gradient: pairs in order of their second index j; each row u
 // gathers its partners e_i and adds sum_p cbar_p (e_i inv_p - c_p e_u / |e_u|^2) to demb[u].
 // pack[p] = (cbar_p, c_p, inv_p = 1 / (|e_i| |e_j|), 0), written by the first pass.
+// One chunk [q0, q1) of gate_cos_bwd_j_kernel's walk.
 template <int NV>
-__global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const float *__restrict__ emb, int64_t n,
-                                                                      int32_t d, const int32_t *__restrict__ pairs,
-                                                                      int64_t cap, const int64_t *__restrict__ P_dev,
-                                                                      const uint64_t *__restrict__ order_j,
-                                                                      const float4 *__restrict__ pack,
-                                                                      float *__restrict__ demb) {
-    const int64_t P = live_count(cap, P_dev);
-    const int l = threadIdx.x & (kGroup - 1);
-    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
-    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
-    const int64_t chunk = ceil_div(P, ngroups);
-    const int64_t q0 = group * chunk, q1 = min(P, q0 + chunk);
+__device__ __forceinline__ void cos_bwd_j_chunk(const float *__restrict__ emb, int64_t n, int32_t d,
+                                                const int32_t *__restrict__ pairs, int64_t P,
+                                                const uint64_t *__restrict__ order_j, const float4 *__restrict__ pack,
+                                                float *__restrict__ demb, int64_t q0, int64_t q1, int l) {
     if (q0 >= q1) return;
     const int d4 = d >> 2;
     float4 eu[NV], acc[NV], old[NV];
@@ -251,6 +254,29 @@ __global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const floa
     if (cur >= 0 && cur < n) {
         const bool ends_here = q1 == P || (int64_t)(order_j[q1] >> 32) != cur;
         flush(started_here && ends_here);
+    }
+}
+
+// LOOP: a lane group walks several capped chunks (a capacity above ngroups x
+// kGateChunkMax pairs); otherwise its one chunk (fewer registers live).
+template <int NV, bool LOOP>
+__global__ __launch_bounds__(kGateThreads) void gate_cos_bwd_j_kernel(const float *__restrict__ emb, int64_t n,
+                                                                      int32_t d, const int32_t *__restrict__ pairs,
+                                                                      int64_t cap, const int64_t *__restrict__ P_dev,
+                                                                      const uint64_t *__restrict__ order_j,
+                                                                      const float4 *__restrict__ pack,
+                                                                      float *__restrict__ demb) {
+    const int64_t P = live_count(cap, P_dev);
+    const int l = threadIdx.x & (kGroup - 1);
+    const int64_t group = ((int64_t)blockIdx.x * kGateThreads + threadIdx.x) / kGroup;
+    const int64_t ngroups = (int64_t)gridDim.x * (kGateThreads / kGroup);
+    const int64_t chunk = gate_chunk(P, ngroups);
+    if (LOOP) {
+        for (int64_t c0 = group * chunk; c0 < P; c0 += ngroups * chunk)
+            cos_bwd_j_chunk<NV>(emb, n, d, pairs, P, order_j, pack, demb, c0, min(P, c0 + chunk), l);
+    } else {
+        const int64_t c0 = group * chunk;
+        cos_bwd_j_chunk<NV>(emb, n, d, pairs, P, order_j, pack, demb, c0, min(P, c0 + chunk), l);
     }
 }
 
