@@ -28,7 +28,7 @@
 namespace subquad {
 
 constexpr int kAlignThreads = 256;
-constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..64)
+constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..stride <= 64)
 constexpr int kMaskCode = 20;          // rows past the shorter sequence's end
 constexpr int kMaskScore = -4096;
 constexpr int kCodes = 21;
@@ -57,9 +57,19 @@ __device__ __forceinline__ bool pair_ok(const int32_t *__restrict__ pairs, int64
     return i >= 0 && j >= 0 && i < n && j < n;
 }
 
-__device__ __forceinline__ int align_key(int lmin, int lmax) {
-    int rb = (max(lmin, 1) + 7) >> 3;  // 1..8
-    return (rb - 1) * 64 + (max(lmax, 1) - 1);
+// Sort key of a pair: its rows bucket (shorter length in (8(rb-1), 8 rb]) times W = stride,
+// plus the longer length - 1 (lengths clamped to 1..W): 7 bits at stride 32, one radix pass.
+__device__ __forceinline__ int align_key(int lmin, int lmax, int W) {
+    const int rb = (min(max(lmin, 1), W) + 7) >> 3;  // 1..ceil(W / 8)
+    return (rb - 1) * W + (min(max(lmax, 1), W) - 1);
+}
+
+// Bits of the largest key at stride W.
+static int align_key_bits(int W) {
+    const int top = ((W + 7) / 8) * W - 1;
+    int b = 1;
+    while ((1 << b) <= top) ++b;
+    return b;
 }
 
 // Pairs to process: cap, or min(*count_dev, cap) when a producer left the count on the device.
@@ -71,13 +81,13 @@ __device__ __forceinline__ int64_t align_count(int64_t cap, const int64_t *__res
 
 __global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restrict__ pairs,
                                                          const int32_t *__restrict__ lens, int64_t n, int64_t cap,
-                                                         const int64_t *__restrict__ P_dev,
+                                                         const int64_t *__restrict__ P_dev, int W,
                                                          uint64_t *__restrict__ rec) {
     const int64_t P = align_count(cap, P_dev);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         int lmin = 1, lmax = 1;
         if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
-        rec[p] = ((uint64_t)align_key(lmin, lmax) << 32) | (uint64_t)p;
+        rec[p] = ((uint64_t)align_key(lmin, lmax, W) << 32) | (uint64_t)p;
     }
 }
 
@@ -386,8 +396,8 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
                                                               const int8_t *__restrict__ subst, int go, int ge,
                                                               int32_t *__restrict__ scores) {
     constexpr int g = ROWS / 8;  // 1..8
-    int64_t lo = g > 1 ? (int64_t)bin_end[(g - 1) * 64 - 1] : 0;
-    int64_t hi = (int64_t)bin_end[g * 64 - 1];
+    int64_t lo = g > 1 ? (int64_t)bin_end[(g - 1) * stride - 1] : 0;
+    int64_t hi = (int64_t)bin_end[g * stride - 1];
     if (hi > P) hi = P;
     if (lo >= hi) return;  // whole grid
     if ((int64_t)blockIdx.x * (kAlignThreads / 64) >= ceil_div(hi - lo, 64)) return;  // whole block
@@ -562,18 +572,19 @@ extern "C" int subquad_self_scores(const uint8_t *seqs, const int32_t *lens, int
 static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride, const int32_t *pairs, int64_t P,
                      const int8_t *subst, int go, int ge, int32_t *scores, uint32_t *scratch, hipStream_t st,
                      int mode = 0, const int64_t *P_dev = nullptr) {
-    // Length sort: records (bucket key << 32 | p) sorted on their 9 key bits by the stable
-    // radix sort; then bin_end[k] = first position whose key exceeds k.
+    // Length sort: records (bucket key << 32 | p) sorted on their key bits (7 at stride 32)
+    // by the stable radix sort; then bin_end[k] = first position whose key exceeds k.
     char *base = reinterpret_cast<char *>(scratch);
     const AlignLayout L = align_layout(P);
     uint64_t *ra = reinterpret_cast<uint64_t *>(base + L.ra);
     uint64_t *rb = reinterpret_cast<uint64_t *>(base + L.rb);
     uint32_t *hist = reinterpret_cast<uint32_t *>(base + L.bins);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
-    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, P_dev, ra);
+    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, P_dev, stride, ra);
     SQ_LAUNCHED("align_keys_kernel");
     uint64_t *sorted = nullptr;
-    int rc = radix_sort_u64(ra, rb, P, P_dev, 32, 9, base + L.radix, L.total - L.radix, st, &sorted, "sort_lengths");
+    int rc = radix_sort_u64(ra, rb, P, P_dev, 32, align_key_bits(stride), base + L.radix, L.total - L.radix, st, &sorted,
+                            "sort_lengths");
     if (rc != SUBQUAD_OK) return rc;
     align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, P_dev, hist);
     SQ_LAUNCHED("align_bins_kernel");
