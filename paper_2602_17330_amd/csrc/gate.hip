@@ -22,10 +22,8 @@
 
 namespace subquad {
 
-#ifndef SQ_GATE_RING
-#define SQ_GATE_RING 2
-#endif
-constexpr int kGateRing = SQ_GATE_RING;  // load slots of the first backward pass
+constexpr int kGateRing = 2;  // load slots of the first backward pass (3 or 4 cost a wave per SIMD)
+static_assert(kGateRing <= 16, "lane u of a pair group stores ring slot u's records");
 constexpr int kWeightStride = 8;  // floats per hidden unit of the LDS weight tables (two float4)
 constexpr int kGateMaxH = 256;
 
@@ -276,10 +274,10 @@ struct TrainOut {
 // per pair pack[p] = (cbar, c, 1 / (|e_i||e_j|), ubar) for the second pass and
 // feat[p] = (s, c, |dL|, [V = V]) for the weight gradients.
 //
-// The gathers run ahead of the arithmetic through a ring of kGateBatch slots: slot u holds
+// The gathers run ahead of the arithmetic through a ring of kGateRing slots: slot u holds
 // the loads of one pair (e_j, j's node record, the alignment score and, when the pair starts
 // a new row, e_i and i's node record), and as soon as its pair is computed the slot is
-// refilled with the pair kGateBatch places further on.  Every gather, including the row of
+// refilled with the pair kGateRing places further on.  Every gather, including the row of
 // the next i, is thus in flight while the pairs before it compute; the pair indices are
 // fetched one ring turn further ahead still.
 template <int NV>
@@ -509,8 +507,8 @@ __global__ __launch_bounds__(kGateThreads) __attribute__((amdgpu_waves_per_eu(3)
     stage_weights(in, wsh);
     const float b2 = in.b2[0];
     // per lane group: the current batch's pack and feat records and fused values
-    __shared__ float4 stage[kGateThreads / kGroup][kGateBatch][2];
-    __shared__ float fstage[kGateThreads / kGroup][kGateBatch];
+    __shared__ float4 stage[kGateThreads / kGroup][kGateRing][2];
+    __shared__ float fstage[kGateThreads / kGroup][kGateRing];
     const int g = threadIdx.x / kGroup;
     double loss_acc = 0.0;
     for (int64_t q0 = group * chunk; q0 < P; q0 += ngroups * chunk) {
