@@ -297,13 +297,18 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
         int64_t idx = base + (int64_t)k * 64 + lane;
         bool valid = idx < n;
         uint32_t d = (uint32_t)(rec[k] >> shift) & dmask;
+        // lanes holding the same digit: for every bit, those whose bit equals this lane's
+        // (the ballot XNOR the lane's bit replicated), as two 32-bit halves
         uint64_t m = __ballot(valid);
+        uint32_t mlo = (uint32_t)m, mhi = (uint32_t)(m >> 32);
 #pragma unroll
         for (int bit = 0; bit < kRadixBits; ++bit) {
-            bool on = (d >> bit) & 1u;
-            uint64_t bal = __ballot(on);
-            m &= on ? bal : ~bal;
+            const uint32_t rep = (uint32_t)((int32_t)(d << (31 - bit)) >> 31);  // 0 or ~0
+            const uint64_t bal = __ballot(rep != 0u);
+            mlo &= ~((uint32_t)bal ^ rep);
+            mhi &= ~((uint32_t)(bal >> 32) ^ rep);
         }
+        m = ((uint64_t)mhi << 32) | mlo;
         uint32_t r = 0;
         if (valid) {
             uint32_t before = wc[w][d];
