@@ -312,6 +312,16 @@ int subquad_gate_train_set_dev(const float *emb, int64_t n, int32_t d, const int
                                float *demb, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * subquad_edit_cost_matrix -- the substitution costs of the edit-distance channel (Appendix
+ * F.3 asks for costs "based on biochemical similarity" and gives no table), doubled so
+ * that the dynamic program runs in integers: cost[a][b] = 0 for a == b, 1 for a
+ * conservative substitution (subst[a][b] > 0), 2 for any other; the matching indel cost is
+ * 2.  subst [20][20] i8 and cost [20][20] i8 are HOST pointers, row-major in residue-code
+ * order; no HIP call is made.  Returns SUBQUAD_ERR_ARG for a null pointer.
+ */
+int subquad_edit_cost_matrix(const int8_t *subst, int8_t *cost);
+
+/*
  * subquad_edit_batch_ws -- the paper's own affinity recurrence (Appendix F.3), a weighted
  * global edit distance, on every pair:
  *   D[x][y] = min(D[x-1][y] + indel, D[x][y-1] + indel, D[x-1][y-1] + cost[a_x][b_y]),

@@ -52,6 +52,7 @@ SIGNATURES = {
                                                   c_p, c_p, c_sz, c_p]),
     "subquad_gate_bwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,
                                         c_p, c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_sz, c_p]),
+    "subquad_edit_cost_matrix": (ctypes.c_int, [c_p, c_p]),
     "subquad_edit_batch_ws": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_p, c_i64, c_p, c_i32, c_p, c_p, c_sz,
                                              c_p]),
     "subquad_gate3_fwd": (ctypes.c_int, [c_p, c_i64, c_i32, c_p, c_p, c_p, c_p, c_p, c_p, c_i64, c_p, c_p,

@@ -392,11 +392,13 @@ def rmt_lambda_max(row_offsets, cols, vals, n: int, tau: float = float("inf"), s
 
 
 def edit_cost_matrix(subst) -> np.ndarray:
-    """Doubled substitution costs for the edit-distance channel: 0 for a match, 1 for a
-    substitution with a positive score (conservative), 2 otherwise; indels cost 2."""
-    S = np.asarray(subst.detach().cpu().numpy() if isinstance(subst, torch.Tensor) else subst, dtype=np.int64)
-    C = np.where(S > 0, 1, 2).astype(np.int8)
-    np.fill_diagonal(C, 0)
+    """Doubled substitution costs of the edit-distance channel (subquad_edit_cost_matrix:
+    0 for a match, 1 for a substitution with a positive score, 2 otherwise; indels cost 2)."""
+    S = np.ascontiguousarray(subst.detach().cpu().numpy() if isinstance(subst, torch.Tensor) else subst, dtype=np.int8)
+    if S.shape != (20, 20):
+        raise ValueError("the substitution matrix must be 20x20")
+    C = np.empty((20, 20), dtype=np.int8)
+    check(lib().subquad_edit_cost_matrix(S.ctypes.data, C.ctypes.data))
     return C
 
 

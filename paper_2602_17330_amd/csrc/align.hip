@@ -729,6 +729,14 @@ extern "C" int subquad_align_batch_noalloc(const uint8_t *seqs, const int32_t *l
     return align_run(seqs, lens, n, stride, pairs, P, subst, gap_open, gap_extend, scores, ws, as_stream(stream));
 }
 
+extern "C" int subquad_edit_cost_matrix(const int8_t *subst, int8_t *cost) {
+    clear_error();
+    SQ_REQUIRE(subst && cost, SUBQUAD_ERR_ARG, "null pointer argument");
+    for (int a = 0; a < 20; ++a)
+        for (int b = 0; b < 20; ++b) cost[a * 20 + b] = (int8_t)(a == b ? 0 : (subst[a * 20 + b] > 0 ? 1 : 2));
+    return SUBQUAD_OK;
+}
+
 extern "C" int subquad_edit_batch_ws(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_t stride,
                                      const int32_t *pairs, int64_t P, const int8_t *cost, int32_t indel,
                                      int32_t *dist, void *ws, size_t ws_bytes, void *stream) {
