@@ -425,20 +425,30 @@ def _rep1m_train_case(P, seed):
                      align=np.ascontiguousarray(oracle_scores("rep1m")[pick]), W1=W1, b1=b1, w2=w2, b2=b2)
 
 
-def test_gate_train_set_rep1m_2p20_against_oracle():
+@pytest.mark.parametrize("P,groups_per_cu", [(1 << 20, None), (1_500_000, 1)])
+def test_gate_train_set_rep1m_2p20_against_oracle(P, groups_per_cu):
     """The writing training pass the benchmark step runs, on 2^20 of the 1M workload's
     candidate pairs (each 16-lane group walks tens of prefetched batches): fused values of
     every pair, the mean loss, the weight gradients and every row of the embedding gradient
     against the float64 oracle.  Hidden units within float32 rounding of the ReLU kink widen
-    the bounds by exactly what flipping each of them changes."""
-    rep, c = _rep1m_train_case(1 << 20, 1005)
+    the bounds by exactly what flipping each of them changes.  With one lane group per CU
+    (256 groups) 1.5M pairs exceed 256 chunks of the 4096-pair cap: every group walks two
+    chunks in rounds and the second backward pass takes its looping form."""
+    from paper_2602_17330_amd import autotune
+    rep, c = _rep1m_train_case(P, 1005)
     lab = rep.family.astype(np.int32)
     args = gpu_args(c)
     W = args[6:]
     g0 = tuple(torch.zeros_like(w) for w in W) + (torch.full_like(args[0], float("nan")),)
-    say(f"gate train set rep1m P={c['pairs'].shape[0]}")
-    fused, loss, grads = sq.api.gate_train(*args, dev(lab), 0.5, grads=g0, set_demb=True)
-    torch.cuda.synchronize()
+    say(f"gate train set rep1m P={c['pairs'].shape[0]} groups_per_cu={groups_per_cu}")
+    old_knob = autotune.get_knob("gate_groups_per_cu")
+    try:
+        if groups_per_cu:
+            autotune.set_knob("gate_groups_per_cu", groups_per_cu)
+        fused, loss, grads = sq.api.gate_train(*args, dev(lab), 0.5, grads=g0, set_demb=True)
+        torch.cuda.synchronize()
+    finally:
+        autotune.set_knob("gate_groups_per_cu", old_knob)
     fused = fused.cpu().numpy()
     grads = [g.cpu().numpy() for g in grads]
     say("gate train set rep1m: oracle forward")
