@@ -14,8 +14,8 @@
 //
 // Mapping to CDNA4: one lane per pair (inter-pair parallelism; CDR3s are short, so a pair
 // fits in registers).  The shorter sequence runs down the unrolled, register-resident
-// rows (ROWS = its length rounded up to 8), the longer one across the column loop.
-// Pairs are first counting-sorted by (rows bucket, longer length), so the lanes of a wave
+// rows (ROWS = its length rounded up to 4), the longer one across the column loop.
+// Pairs are first radix-sorted by (rows bucket, longer length), so the lanes of a wave
 // have the same unroll and nearly the same trip count.  Substitution scores come from an
 // LDS table that packs S(a_x, c) and S(a_x+1, c) for a row pair and a column residue c
 // into one 32-bit word (one ds_read per two cells).
@@ -28,7 +28,10 @@
 namespace subquad {
 
 constexpr int kAlignThreads = 256;
-constexpr int kAlignKeyBins = 8 * 64;  // rows bucket (1..8) x longer length (1..stride <= 64)
+// Rows per bucket: a kernel of ROWS rows takes the shorter lengths in (ROWS - step, ROWS],
+// step 4 from kAlignFinePairs pairs (less row padding), 8 below (half the launches).
+constexpr int kAlignFinePairs = 1 << 24;
+constexpr int kAlignKeyBins = 16 * 64;  // rows bucket (1..16) x longer length (1..stride <= 64)
 constexpr int kMaskCode = 20;          // rows past the shorter sequence's end
 constexpr int kMaskScore = -4096;
 constexpr int kCodes = 21;
@@ -57,16 +60,17 @@ __device__ __forceinline__ bool pair_ok(const int32_t *__restrict__ pairs, int64
     return i >= 0 && j >= 0 && i < n && j < n;
 }
 
-// Sort key of a pair: its rows bucket (shorter length in (8(rb-1), 8 rb]) times W = stride,
-// plus the longer length - 1 (lengths clamped to 1..W): 7 bits at stride 32, one radix pass.
-__device__ __forceinline__ int align_key(int lmin, int lmax, int W) {
-    const int rb = (min(max(lmin, 1), W) + 7) >> 3;  // 1..ceil(W / 8)
+// Sort key of a pair: its rows bucket (shorter length in (step(rb-1), step rb]) times
+// W = stride, plus the longer length - 1 (lengths clamped to 1..W): at stride 32, 7 bits
+// (step 8) or 8 (step 4), one radix pass.
+__device__ __forceinline__ int align_key(int lmin, int lmax, int W, int step) {
+    const int rb = (min(max(lmin, 1), W) + step - 1) / step;  // 1..ceil(W / step)
     return (rb - 1) * W + (min(max(lmax, 1), W) - 1);
 }
 
 // Bits of the largest key at stride W.
-static int align_key_bits(int W) {
-    const int top = ((W + 7) / 8) * W - 1;
+static int align_key_bits(int W, int step) {
+    const int top = ((W + step - 1) / step) * W - 1;
     int b = 1;
     while ((1 << b) <= top) ++b;
     return b;
@@ -81,13 +85,13 @@ __device__ __forceinline__ int64_t align_count(int64_t cap, const int64_t *__res
 
 __global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restrict__ pairs,
                                                          const int32_t *__restrict__ lens, int64_t n, int64_t cap,
-                                                         const int64_t *__restrict__ P_dev, int W,
+                                                         const int64_t *__restrict__ P_dev, int W, int step,
                                                          uint64_t *__restrict__ rec) {
     const int64_t P = align_count(cap, P_dev);
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
         int lmin = 1, lmax = 1;
         if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
-        rec[p] = ((uint64_t)align_key(lmin, lmax, W) << 32) | (uint64_t)p;
+        rec[p] = ((uint64_t)align_key(lmin, lmax, W, step) << 32) | (uint64_t)p;
     }
 }
 
@@ -384,7 +388,7 @@ __device__ __forceinline__ int ed_lane(const uint8_t *__restrict__ arow, int la,
     return la == 0 ? lb * indel : res;
 }
 
-// Pairs of one rows bucket (shorter length in (ROWS-8, ROWS]), taken in the length order
+// Pairs of one rows bucket (shorter length in (ROWS - step, ROWS]), taken in the length order
 // (one metadata record per sorted position): the bucket's range is read from the sort's
 // end offsets on the device, so the launch needs no host synchronisation.
 template <int ROWS, int MODE>
@@ -394,8 +398,8 @@ __global__ __launch_bounds__(kAlignThreads) void align_kernel(const uint8_t *__r
                                                               int64_t P, const uint4 *__restrict__ meta,
                                                               const uint32_t *__restrict__ bin_end,
                                                               const int8_t *__restrict__ subst, int go, int ge,
-                                                              int32_t *__restrict__ scores) {
-    constexpr int g = ROWS / 8;  // 1..8
+                                                              int32_t *__restrict__ scores, int step) {
+    const int g = ROWS / step;  // 1..16 (ROWS a multiple of step)
     int64_t lo = g > 1 ? (int64_t)bin_end[(g - 1) * stride - 1] : 0;
     int64_t hi = (int64_t)bin_end[g * stride - 1];
     if (hi > P) hi = P;
@@ -580,11 +584,12 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
     uint64_t *rb = reinterpret_cast<uint64_t *>(base + L.rb);
     uint32_t *hist = reinterpret_cast<uint32_t *>(base + L.bins);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 8);
-    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, P_dev, stride, ra);
+    const int step = P >= kAlignFinePairs ? 4 : 8;  // rows per bucket
+    align_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, lens, n, P, P_dev, stride, step, ra);
     SQ_LAUNCHED("align_keys_kernel");
     uint64_t *sorted = nullptr;
-    int rc = radix_sort_u64(ra, rb, P, P_dev, 32, align_key_bits(stride), base + L.radix, L.total - L.radix, st, &sorted,
-                            "sort_lengths");
+    int rc = radix_sort_u64(ra, rb, P, P_dev, 32, align_key_bits(stride, step), base + L.radix, L.total - L.radix, st,
+                            &sorted, "sort_lengths");
     if (rc != SUBQUAD_OK) return rc;
     align_bins_kernel<<<1, kAlignKeyBins, 0, st>>>(sorted, P, P_dev, hist);
     SQ_LAUNCHED("align_bins_kernel");
@@ -603,17 +608,25 @@ static int align_run(const uint8_t *seqs, const int32_t *lens, int64_t n, int32_
         ProfScope prof("align_kernel", st);
 #define SQ_ROWS(R)                                                                                             \
     align_kernel<R, 0><<<ablocks((const void *)align_kernel<R, 0>), kAlignThreads, 0, st>>>(                   \
-        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores);
+        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores, step);
+        if (step == 4) { SQ_ROWS(4) SQ_ROWS(12) SQ_ROWS(20) SQ_ROWS(28) }
         SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
-        if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
+        if (stride > 32) {
+            if (step == 4) { SQ_ROWS(36) SQ_ROWS(44) SQ_ROWS(52) SQ_ROWS(60) }
+            SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64)
+        }
 #undef SQ_ROWS
     } else {
         ProfScope prof("edit_kernel", st);
 #define SQ_ROWS(R)                                                                                             \
     align_kernel<R, 1><<<ablocks((const void *)align_kernel<R, 1>), kAlignThreads, 0, st>>>(                   \
-        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores);
+        seqs, lens, n, stride, pairs, P, meta, bin_end, subst, go, ge, scores, step);
+        if (step == 4) { SQ_ROWS(4) SQ_ROWS(12) SQ_ROWS(20) SQ_ROWS(28) }
         SQ_ROWS(8) SQ_ROWS(16) SQ_ROWS(24) SQ_ROWS(32)
-        if (stride > 32) { SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64) }
+        if (stride > 32) {
+            if (step == 4) { SQ_ROWS(36) SQ_ROWS(44) SQ_ROWS(52) SQ_ROWS(60) }
+            SQ_ROWS(40) SQ_ROWS(48) SQ_ROWS(56) SQ_ROWS(64)
+        }
 #undef SQ_ROWS
     }
     SQ_LAUNCHED("align_kernel");

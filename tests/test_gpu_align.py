@@ -151,6 +151,23 @@ def test_zipf100k_pairs_sampled(S):
     assert np.array_equal(got[sel], sw_oracle(r.seqs, r.lens, pairs[sel], S))
 
 
+def test_fine_row_buckets_sampled(S):
+    """From 2^24 pairs the alignment takes rows buckets of 4 instead of 8 (less padding, more
+    launches): over 2^24 family-heavy pairs of the 100k-sequence repertoire (shorter lengths
+    8-25, every bucket), a seeded sample of 200,000 scores against the oracle, and every
+    score of the first and last 50,000 sorted positions' worth of pairs equal to the same
+    pairs aligned in a call below the threshold."""
+    r = workload("zipf100k")
+    pairs = synth.random_pairs(r.n, 18_500_000, 11, family=r.family, same_frac=0.7)
+    assert pairs.shape[0] >= 1 << 24  # (duplicates drawn are dropped)
+    say(f"align fine buckets P={pairs.shape[0]}")
+    got = _gpu(r.seqs, r.lens, pairs, S)
+    sel = synth.sample_rows(pairs.shape[0], 200_000, 4)
+    assert np.array_equal(got[sel], sw_oracle(r.seqs, r.lens, pairs[sel], S))
+    head = np.ascontiguousarray(pairs[:2_000_000])
+    assert np.array_equal(got[:2_000_000], _gpu(r.seqs, r.lens, head, S))
+
+
 def test_rep1m_pairs_sampled(S):
     """Full-size workload: 4M family-heavy pairs over 1M sequences, sampled check."""
     r = workload("rep1m")
