@@ -73,8 +73,12 @@ int32_t subquad_get_knob(int32_t knob);             /* current value, -1 if unkn
  * and writes one line per kernel name, "name launches total_ms\n", into buf (host, len
  * bytes, always NUL-terminated); it returns the bytes needed (excluding the NUL).
  * Enabling (on != 0) or disabling clears the records.  Not for use under graph capture.
+ * subquad_profile_only limits the timing to the launches of the kernel named `name` (host
+ * string, copied), so that the rest of the work runs with no events between its launches;
+ * null or "" times every kernel again.  It clears the records too.
  */
 int subquad_profile_enable(int32_t on);
+int subquad_profile_only(const char *name);
 int64_t subquad_profile_report(char *buf, size_t len);
 
 /*

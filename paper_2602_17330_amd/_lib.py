@@ -21,6 +21,7 @@ SIGNATURES = {
     "subquad_set_knob": (ctypes.c_int, [c_i32, c_i32]),
     "subquad_get_knob": (c_i32, [c_i32]),
     "subquad_profile_enable": (ctypes.c_int, [c_i32]),
+    "subquad_profile_only": (ctypes.c_int, [ctypes.c_char_p]),
     "subquad_profile_report": (c_i64, [ctypes.c_char_p, c_sz]),
     "subquad_check_seqs": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_p, c_p]),
     "subquad_minhash": (ctypes.c_int, [c_p, c_p, c_i64, c_i32, c_i32, c_i32, c_u64, c_p, c_p]),
@@ -110,6 +111,11 @@ def check(status: int) -> None:
 
 def profile_enable(on: bool = True) -> None:
     check(lib().subquad_profile_enable(1 if on else 0))
+
+
+def profile_only(name: str | None = None) -> None:
+    """Time only the launches of kernel `name` while timing is on (None: every kernel)."""
+    check(lib().subquad_profile_only(name.encode() if name else None))
 
 
 def profile_report() -> dict:

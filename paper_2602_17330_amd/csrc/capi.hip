@@ -90,6 +90,7 @@ static std::mutex g_prof_mu;
 static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_prof_pool;  // events are reused, so timing adds no creation cost
 static std::atomic<bool> g_prof_on{false};
+static std::string g_prof_only;  // when not empty, only launches of this kernel are timed
 
 static void prof_clear_locked() {
     for (auto &r : g_prof) {
@@ -110,9 +111,10 @@ static hipEvent_t prof_event_locked() {
     return e;
 }
 
-int prof_begin(hipStream_t st) {
+int prof_begin(const char *name, hipStream_t st) {
     if (!g_prof_on.load(std::memory_order_relaxed)) return -1;
     std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_only.empty() && g_prof_only != name) return -1;
     ProfRec r;
     r.a = prof_event_locked();
     r.b = prof_event_locked();
@@ -165,6 +167,14 @@ extern "C" int subquad_profile_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     prof_clear_locked();
     g_prof_on.store(on != 0);
+    return SUBQUAD_OK;
+}
+
+extern "C" int subquad_profile_only(const char *name) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_clear_locked();
+    g_prof_only = name ? name : "";
     return SUBQUAD_OK;
 }
 

@@ -58,16 +58,16 @@ int resident_blocks_per_cu(const void *kernel);
 // Launch-shape knob value (default when unset).
 int knob(int which);
 
-// Opt-in per-kernel event timing: prof_begin returns a token (or -1 when disabled) and
-// prof_end records the closing event for it.
-int prof_begin(hipStream_t st);
+// Opt-in per-kernel event timing: prof_begin returns a token (or -1 when timing is off, or
+// limited to another kernel) and prof_end records the closing event for it.
+int prof_begin(const char *name, hipStream_t st);
 void prof_end(int token, const char *name, hipStream_t st);
 
 struct ProfScope {
     int tok;
     const char *name;
     hipStream_t st;
-    ProfScope(const char *n, hipStream_t s) : tok(prof_begin(s)), name(n), st(s) {}
+    ProfScope(const char *n, hipStream_t s) : tok(prof_begin(n, s)), name(n), st(s) {}
     ~ProfScope() { prof_end(tok, name, st); }
 };
 

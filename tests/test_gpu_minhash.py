@@ -73,3 +73,28 @@ def test_rep1m_full_exact():
     torch.cuda.synchronize()
     ref = oracle_sig("rep1m")
     assert np.array_equal(got, ref)
+
+
+def test_profile_only_times_the_named_kernel():
+    """Kernel timing limited to one kernel records that kernel's launches and no other."""
+    from paper_2602_17330_amd import _lib
+    r = synth.tiny(n_families=20, fam_size=5)
+    s, l = dev(r.seqs), dev(r.lens)
+    say("profile_only minhash3_kernel")
+    try:
+        _lib.profile_enable(True)
+        _lib.profile_only("minhash3_kernel")
+        sig = sq.minhash(s, l, 64)
+        sq.lsh_candidates(sig, 16, 4)
+        torch.cuda.synchronize()
+        only = _lib.profile_report()
+        _lib.profile_only(None)
+        sq.minhash(s, l, 64)
+        sq.lsh_candidates(sig, 16, 4)
+        torch.cuda.synchronize()
+        every = _lib.profile_report()
+    finally:
+        _lib.profile_only(None)
+        _lib.profile_enable(False)
+    assert set(only) == {"minhash3_kernel"} and only["minhash3_kernel"][0] == 1
+    assert "minhash3_kernel" in every and "lsh_keys_kernel" in every
