@@ -77,6 +77,9 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *_
     }
 }
 
+// VEC: data is 16-byte aligned, so a thread moves its entries as 16-byte words (a wave's
+// loads then cover whole lines instead of one word in every 64 bytes).
+template <bool VEC>
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ data, int64_t count,
                                                                   const uint32_t *__restrict__ partial,
                                                                   const int64_t *__restrict__ live) {
@@ -84,22 +87,41 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__re
     __shared__ uint32_t wt[4];
     // thread t owns kScanItems consecutive entries
     int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const bool whole = VEC && base + kScanItems <= count;
     uint32_t v[kScanItems];
     uint32_t s = 0;
+    if (whole) {
+        const uint4 *d4 = reinterpret_cast<const uint4 *>(data + base);
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) v[k] = data[clamp_index(base + k, count)];
+        for (int k = 0; k < kScanItems / 4; ++k) {
+            const uint4 q = d4[k];
+            v[4 * k] = q.x;
+            v[4 * k + 1] = q.y;
+            v[4 * k + 2] = q.z;
+            v[4 * k + 3] = q.w;
+        }
+    } else {
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k >= count) v[k] = 0;
-        s += v[k];
+        for (int k = 0; k < kScanItems; ++k) v[k] = base + k < count ? data[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t inc = block_inclusive_scan(s, wt);
     uint32_t run = partial[blockIdx.x] + inc - s;
+    uint32_t out[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        int64_t idx = base + k;
-        if (idx < count) data[idx] = run;
+        out[k] = run;
         run += v[k];
+    }
+    if (whole) {
+        uint4 *d4 = reinterpret_cast<uint4 *>(data + base);
+#pragma unroll
+        for (int k = 0; k < kScanItems / 4; ++k) d4[k] = make_uint4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < count) data[base + k] = out[k];
     }
 }
 
@@ -116,7 +138,8 @@ static int scan_exclusive_u32_live(uint32_t *data, int64_t count, const int64_t 
     SQ_LAUNCHED("scan_reduce_kernel");
     scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks, live);
     SQ_LAUNCHED("scan_partials_kernel");
-    scan_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
+    if (((uintptr_t)data & 15) == 0) scan_apply_kernel<true><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
+    else scan_apply_kernel<false><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
     SQ_LAUNCHED("scan_apply_kernel");
     return SUBQUAD_OK;
 }
