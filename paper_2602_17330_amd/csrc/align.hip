@@ -47,6 +47,19 @@ __device__ __forceinline__ int max3_asm(int a, int b, int c) {
     return r;
 }
 
+__device__ __forceinline__ void pair_lengths(const int32_t *__restrict__ pairs, const int32_t *__restrict__ lens,
+                                             int64_t p, int &lmin, int &lmax) {
+    int la = lens[pairs[2 * p]], lb = lens[pairs[2 * p + 1]];
+    lmin = min(max(la, 0), 64);
+    lmax = min(max(lb, 0), 64);
+    if (lmin > lmax) { int t = lmin; lmin = lmax; lmax = t; }
+}
+
+__device__ __forceinline__ bool pair_ok(const int32_t *__restrict__ pairs, int64_t n, int64_t p) {
+    int32_t i = pairs[2 * p], j = pairs[2 * p + 1];
+    return i >= 0 && j >= 0 && i < n && j < n;
+}
+
 // Sort key of a pair: its rows bucket (shorter length in (step(rb-1), step rb]) times
 // W = stride, plus the longer length - 1 (lengths clamped to 1..W): at stride 32, 7 bits
 // (step 8) or 8 (step 4), one radix pass.
@@ -63,9 +76,6 @@ static int align_key_bits(int W, int step) {
     return b;
 }
 
-// Pairs (or sorted positions) a thread of the key and metadata kernels gathers at once.
-constexpr int kAlignGatherUnroll = 4;
-
 // Pairs to process: cap, or min(*count_dev, cap) when a producer left the count on the device.
 __device__ __forceinline__ int64_t align_count(int64_t cap, const int64_t *__restrict__ count_dev) {
     if (!count_dev) return cap;
@@ -78,44 +88,10 @@ __global__ __launch_bounds__(256) void align_keys_kernel(const int32_t *__restri
                                                          const int64_t *__restrict__ P_dev, int W, int step,
                                                          uint64_t *__restrict__ rec) {
     const int64_t P = align_count(cap, P_dev);
-    const int64_t G = (int64_t)gridDim.x * blockDim.x;
-    // kAlignGatherUnroll pairs at a time, each stage's loads issued together (the pair, then
-    // both lengths), so that a thread has more than one chain of dependent gathers in flight
-    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p0 < P; p0 += kAlignGatherUnroll * G) {
-        int32_t pi[kAlignGatherUnroll], pj[kAlignGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            const int64_t p = min(p0 + u * G, P - 1);
-            pi[u] = pairs[2 * p];
-            pj[u] = pairs[2 * p + 1];
-        }
-        int li[kAlignGatherUnroll], lj[kAlignGatherUnroll];
-        bool ok[kAlignGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            ok[u] = pi[u] >= 0 && pj[u] >= 0 && pi[u] < n && pj[u] < n;
-            li[u] = lj[u] = 1;
-        }
-        if (n > 0) {  // (uniform) every length load issues; a pair out of range reads row 0's
-#pragma unroll
-            for (int u = 0; u < kAlignGatherUnroll; ++u) {
-                li[u] = lens[ok[u] ? pi[u] : 0];
-                lj[u] = lens[ok[u] ? pj[u] : 0];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            const int64_t p = p0 + u * G;
-            if (p >= P) break;
-            int lmin = min(max(li[u], 0), 64), lmax = min(max(lj[u], 0), 64);
-            if (lmin > lmax) {
-                const int t = lmin;
-                lmin = lmax;
-                lmax = t;
-            }
-            if (!ok[u]) lmin = lmax = 1;
-            rec[p] = ((uint64_t)align_key(lmin, lmax, W, step) << 32) | (uint64_t)p;
-        }
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        int lmin = 1, lmax = 1;
+        if (pair_ok(pairs, n, p)) pair_lengths(pairs, lens, p, lmin, lmax);
+        rec[p] = ((uint64_t)align_key(lmin, lmax, W, step) << 32) | (uint64_t)p;
     }
 }
 
@@ -144,47 +120,18 @@ __global__ __launch_bounds__(256) void align_meta_kernel(const uint64_t *__restr
                                                          int64_t cap, const int64_t *__restrict__ P_dev,
                                                          uint4 *__restrict__ meta) {
     const int64_t P = align_count(cap, P_dev);
-    const int64_t G = (int64_t)gridDim.x * blockDim.x;
-    // kAlignGatherUnroll positions at a time: the records, then the pairs, then the lengths,
-    // each stage's loads issued together
-    for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < P; q0 += kAlignGatherUnroll * G) {
-        uint32_t p[kAlignGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) p[u] = (uint32_t)srec[min(q0 + u * G, P - 1)];
-        int32_t pi[kAlignGatherUnroll], pj[kAlignGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            pi[u] = pairs[2 * (int64_t)p[u]];
-            pj[u] = pairs[2 * (int64_t)p[u] + 1];
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < P; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = (uint32_t)srec[q];
+        const int32_t i = pairs[2 * (int64_t)p], j = pairs[2 * (int64_t)p + 1];
+        uint4 m = make_uint4(0u, 0u, kMetaBad, p);
+        if (i >= 0 && j >= 0 && i < n && j < n) {
+            const int li = min(max(lens[i], 0), stride), lj = min(max(lens[j], 0), stride);
+            const bool swap = li > lj;
+            m.x = (uint32_t)(swap ? j : i);
+            m.y = (uint32_t)(swap ? i : j);
+            m.z = (uint32_t)(swap ? lj : li) | (uint32_t)(swap ? li : lj) << 8 | (swap ? 1u << 16 : 0u);
         }
-        int li[kAlignGatherUnroll], lj[kAlignGatherUnroll];
-        bool ok[kAlignGatherUnroll];
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            ok[u] = pi[u] >= 0 && pj[u] >= 0 && pi[u] < n && pj[u] < n;
-            li[u] = lj[u] = 0;
-        }
-        if (n > 0) {  // (uniform) every length load issues; a pair out of range reads row 0's
-#pragma unroll
-            for (int u = 0; u < kAlignGatherUnroll; ++u) {
-                li[u] = lens[ok[u] ? pi[u] : 0];
-                lj[u] = lens[ok[u] ? pj[u] : 0];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kAlignGatherUnroll; ++u) {
-            const int64_t q = q0 + u * G;
-            if (q >= P) break;
-            uint4 m = make_uint4(0u, 0u, kMetaBad, p[u]);
-            if (ok[u]) {
-                const int a = min(max(li[u], 0), stride), b = min(max(lj[u], 0), stride);
-                const bool swap = a > b;
-                m.x = (uint32_t)(swap ? pj[u] : pi[u]);
-                m.y = (uint32_t)(swap ? pi[u] : pj[u]);
-                m.z = (uint32_t)(swap ? b : a) | (uint32_t)(swap ? a : b) << 8 | (swap ? 1u << 16 : 0u);
-            }
-            meta[q] = m;
-        }
+        meta[q] = m;
     }
 }
 

@@ -6,7 +6,9 @@
 // with wave ballots (the eight digit bits give each lane the mask of lanes holding the same
 // digit; its rank is the popcount of the lower lanes in that mask) and per-wave digit
 // counters in LDS, stages the tile in LDS in sorted order, and then writes each digit's run
-// with consecutive threads so that global stores are contiguous.
+// with consecutive threads so that global stores are contiguous.  The scan itself is two
+// launches, chunk totals and then the chunks, each block of the second adding up the totals
+// before its chunk (a third launch scans the totals first when there are more than 1024).
 #include "radix.h"
 
 namespace subquad {
@@ -14,6 +16,7 @@ namespace subquad {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;
+constexpr int64_t kScanSumChunks = 1024;  // up to this many chunks, apply blocks add up their prefix
 
 // idx, or the last valid index when idx is past the end (count >= 1): lets a loop issue all
 // of its loads unconditionally, masking the values afterwards.
@@ -79,12 +82,22 @@ __global__ __launch_bounds__(kScanThreads) void scan_partials_kernel(uint32_t *_
 
 // VEC: data is 16-byte aligned, so a thread moves its entries as 16-byte words (a wave's
 // loads then cover whole lines instead of one word in every 64 bytes).
-template <bool VEC>
+// SUM: partial holds the chunks' raw totals (no scan_partials_kernel ran) and each block adds
+// up those before its own; for at most kScanSumChunks chunks that costs less than a launch.
+template <bool VEC, bool SUM>
 __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ data, int64_t count,
                                                                   const uint32_t *__restrict__ partial,
                                                                   const int64_t *__restrict__ live) {
     if (live && *live <= 0) return;
     __shared__ uint32_t wt[4];
+    __shared__ uint32_t before;
+    if (SUM) {  // the chunks before this block's, summed over the block
+        uint32_t acc = 0;
+        for (int c = threadIdx.x; c < (int)blockIdx.x; c += kScanThreads) acc += partial[c];
+        const uint32_t ps = block_inclusive_scan(acc, wt);
+        if (threadIdx.x == kScanThreads - 1) before = ps;
+        __syncthreads();
+    }
     // thread t owns kScanItems consecutive entries
     int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     const bool whole = VEC && base + kScanItems <= count;
@@ -107,7 +120,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__re
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t inc = block_inclusive_scan(s, wt);
-    uint32_t run = partial[blockIdx.x] + inc - s;
+    uint32_t run = (SUM ? before : partial[blockIdx.x]) + inc - s;
     uint32_t out[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
@@ -136,10 +149,17 @@ static int scan_exclusive_u32_live(uint32_t *data, int64_t count, const int64_t 
     uint32_t *partial = static_cast<uint32_t *>(scratch);
     scan_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
     SQ_LAUNCHED("scan_reduce_kernel");
-    scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks, live);
-    SQ_LAUNCHED("scan_partials_kernel");
-    if (((uintptr_t)data & 15) == 0) scan_apply_kernel<true><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
-    else scan_apply_kernel<false><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count, partial, live);
+    const bool vec = ((uintptr_t)data & 15) == 0;
+    const unsigned g = (unsigned)chunks;
+    if (chunks <= kScanSumChunks) {
+        if (vec) scan_apply_kernel<true, true><<<g, kScanThreads, 0, st>>>(data, count, partial, live);
+        else scan_apply_kernel<false, true><<<g, kScanThreads, 0, st>>>(data, count, partial, live);
+    } else {
+        scan_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks, live);
+        SQ_LAUNCHED("scan_partials_kernel");
+        if (vec) scan_apply_kernel<true, false><<<g, kScanThreads, 0, st>>>(data, count, partial, live);
+        else scan_apply_kernel<false, false><<<g, kScanThreads, 0, st>>>(data, count, partial, live);
+    }
     SQ_LAUNCHED("scan_apply_kernel");
     return SUBQUAD_OK;
 }
@@ -207,10 +227,20 @@ __global__ __launch_bounds__(kScanThreads) void scan64_partials_kernel(uint64_t 
     }
 }
 
+// SUM as in scan_apply_kernel: partial holds raw chunk totals, added up here.
+template <bool SUM>
 __global__ __launch_bounds__(kScanThreads) void scan64_apply_kernel(uint64_t *__restrict__ data, int64_t cap,
                                                                     const uint64_t *__restrict__ count_dev,
                                                                     const uint64_t *__restrict__ partial) {
     __shared__ uint64_t wt[4];
+    __shared__ uint64_t before;
+    if (SUM) {
+        uint64_t acc = 0;
+        for (int c = threadIdx.x; c < (int)blockIdx.x; c += kScanThreads) acc += partial[c];
+        const uint64_t ps = block_inclusive_scan64(acc, wt);
+        if (threadIdx.x == kScanThreads - 1) before = ps;
+        __syncthreads();
+    }
     const int64_t count = count_of(cap, count_dev);
     int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     uint64_t v[kScanItems];
@@ -225,7 +255,7 @@ __global__ __launch_bounds__(kScanThreads) void scan64_apply_kernel(uint64_t *__
         s += v[k];
     }
     uint64_t inc = block_inclusive_scan64(s, wt);
-    uint64_t run = partial[blockIdx.x] + inc - s;
+    uint64_t run = (SUM ? before : partial[blockIdx.x]) + inc - s;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         int64_t idx = base + k;
@@ -244,9 +274,13 @@ int scan_exclusive_u64(uint64_t *data, int64_t count_cap, const uint64_t *count_
     uint64_t *partial = static_cast<uint64_t *>(scratch);
     scan64_reduce_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
     SQ_LAUNCHED("scan64_reduce_kernel");
-    scan64_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks);
-    SQ_LAUNCHED("scan64_partials_kernel");
-    scan64_apply_kernel<<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
+    if (chunks <= kScanSumChunks) {
+        scan64_apply_kernel<true><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
+    } else {
+        scan64_partials_kernel<<<1, kScanThreads, 0, st>>>(partial, chunks);
+        SQ_LAUNCHED("scan64_partials_kernel");
+        scan64_apply_kernel<false><<<(unsigned)chunks, kScanThreads, 0, st>>>(data, count_cap, count_dev, partial);
+    }
     SQ_LAUNCHED("scan64_apply_kernel");
     return SUBQUAD_OK;
 }
