@@ -168,6 +168,25 @@ def test_fine_row_buckets_sampled(S):
     assert np.array_equal(got[:2_000_000], _gpu(r.seqs, r.lens, head, S))
 
 
+def test_length_sort_with_long_scan(S):
+    """2^26 + 2^20 pairs: the length sort's histogram scan then has more than 1024 chunks of
+    4096 counters, so it takes its three-launch form (a single-block scan of the chunk totals
+    between the two passes).  Random pairs of the 5,000-sequence workload; a seeded sample of
+    100,000 scores against the oracle, and the first 1,000,000 equal to the same pairs aligned
+    alone (a scan of few chunks)."""
+    r = workload("small5k")
+    P = (1 << 26) + (1 << 20)
+    assert P * 256 // 4096 // 4096 > 1024  # counters of the one 8-bit pass, in chunks
+    rng = np.random.default_rng(2026)
+    pairs = rng.integers(0, r.n, (P, 2), dtype=np.int32)
+    say(f"align long scan P={P}")
+    got = _gpu(r.seqs, r.lens, pairs, S)
+    sel = synth.sample_rows(P, 100_000, 6)
+    assert np.array_equal(got[sel], sw_oracle(r.seqs, r.lens, pairs[sel], S))
+    head = np.ascontiguousarray(pairs[:1_000_000])
+    assert np.array_equal(got[:1_000_000], _gpu(r.seqs, r.lens, head, S))
+
+
 def test_rep1m_pairs_sampled(S):
     """Full-size workload: 4M family-heavy pairs over 1M sequences, sampled check."""
     r = workload("rep1m")
