@@ -111,6 +111,24 @@ static hipEvent_t prof_event_locked() {
     return e;
 }
 
+int side_stream(SideStream **out) {
+    constexpr int kMaxDevices = 64;
+    int dev = 0;
+    SQ_HIP(hipGetDevice(&dev));
+    SQ_REQUIRE(dev >= 0 && dev < kMaxDevices, SUBQUAD_ERR_HIP, "device %d out of range", dev);
+    static thread_local SideStream side[kMaxDevices];
+    SideStream &ss = side[dev];
+    if (!ss.s) {
+        SideStream made;
+        SQ_HIP(hipStreamCreateWithFlags(&made.s, hipStreamNonBlocking));
+        SQ_HIP(hipEventCreateWithFlags(&made.fork, hipEventDisableTiming));
+        SQ_HIP(hipEventCreateWithFlags(&made.done, hipEventDisableTiming));
+        ss = made;
+    }
+    *out = &ss;
+    return SUBQUAD_OK;
+}
+
 int prof_begin(const char *name, hipStream_t st) {
     if (!g_prof_on.load(std::memory_order_relaxed)) return -1;
     std::lock_guard<std::mutex> lk(g_prof_mu);

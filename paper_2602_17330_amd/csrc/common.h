@@ -58,6 +58,17 @@ int resident_blocks_per_cu(const void *kernel);
 // Launch-shape knob value (default when unset).
 int knob(int which);
 
+// A second stream on the current device for the calling host thread (non-blocking, default
+// priority), with events to fork work off a caller's stream and join it back: record on one
+// stream, wait on the other.  Created on first use and kept until the process ends.  Work
+// forked this way joins the caller's stream before the entry point returns, so a captured
+// graph gets it as a parallel branch.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, done = nullptr;
+};
+int side_stream(SideStream **out);
+
 // Opt-in per-kernel event timing: prof_begin returns a token (or -1 when timing is off, or
 // limited to another kernel) and prof_end records the closing event for it.
 int prof_begin(const char *name, hipStream_t st);

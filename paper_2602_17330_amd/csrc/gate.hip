@@ -716,6 +716,7 @@ struct GateOrders {
     const uint64_t *order_i;    // the same sorted by i (meaningful only when unsorted[0] != 0)
     const uint64_t *order_j;    // (j << 32 | p) sorted by j
     const int64_t *unsorted;    // [0]: 1 when the pairs are not in order of i, [1]: records the i sort takes
+    hipEvent_t j_ready;         // recorded on the second stream once order_j is built
 };
 
 __global__ void fill_f32_kernel(float *__restrict__ x, int64_t count, float v) {
@@ -790,6 +791,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
                                                                              in.d >> 2, demb);                     \
                 SQ_LAUNCHED("gate_set_rows_prep_kernel");                                                          \
             }                                                                                                      \
+            SQ_HIP(hipStreamWaitEvent(st, o.j_ready, 0)); /* the j order, built on the second stream */           \
             ProfScope prof("gate_bwd_kernel", st);                                                                 \
             kern<<<(unsigned)blocks, kGateThreads, 0, st>>>(in, gf, o.order_nat, o.order_i, o.unsorted, pack, feat,  \
                                                             demb, tr);                                             \
@@ -832,7 +834,7 @@ static int gate_bwd_nv(const GateIn &in, const float *gf, const TrainOut &tr, in
 static int64_t gate_max_blocks() { return (int64_t)device_cus() * 8; }
 
 struct GateBwdLayout {
-    size_t wpart, ra, rb, rc, rd, pack, feat, node, lpart, flags, radix, total;
+    size_t wpart, ra, rb, rc, rd, pack, feat, node, lpart, flags, radix, radix_j, total;
 };
 
 static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
@@ -850,6 +852,7 @@ static GateBwdLayout gate_bwd_layout(int32_t H, int64_t P, int64_t n) {
     L.lpart = take(sizeof(double) * (size_t)gate_max_blocks());
     L.flags = take(sizeof(int64_t) * 2);
     L.radix = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
+    L.radix_j = take(radix_scratch_bytes(std::max<int64_t>(P, 1)));
     L.total = off;
     return L;
 }
@@ -878,7 +881,9 @@ __global__ void gate_sorted_count_kernel(int64_t *__restrict__ flags, int64_t ca
 // Orders of the pair indices by their first and by their second index (stable, so each row
 // keeps the input order) for the two backward passes.  When the pairs already come in order
 // of i (the candidate lists do), the i sort is given no records and the first pass walks the
-// pairs as they are.
+// pairs as they are.  The two orders depend only on the pairs: the j order is built on a
+// second stream (its own sort scratch) while this one builds the i order and zeroes rows;
+// the first pass waits for both (o.j_ready), so the two chains of small launches overlap.
 static int gate_pair_orders(const int32_t *pairs, int64_t P, const int64_t *P_dev, int64_t n, char *ws,
                             const GateBwdLayout &L, hipStream_t st, GateOrders &o) {
     uint64_t *ra = reinterpret_cast<uint64_t *>(ws + L.ra), *rb = reinterpret_cast<uint64_t *>(ws + L.rb);
@@ -886,6 +891,18 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, const int64_t *P_de
     int64_t *flags = reinterpret_cast<int64_t *>(ws + L.flags);
     const int64_t blocks = std::min<int64_t>(ceil_div(P, 256), (int64_t)device_cus() * 16);
     const int bits = key_bits_for(n);
+    const size_t sort_scratch = radix_scratch_bytes(std::max<int64_t>(P, 1));
+    SideStream *side = nullptr;
+    int rc_ = side_stream(&side);
+    if (rc_ != SUBQUAD_OK) return rc_;
+    SQ_HIP(hipEventRecord(side->fork, st));
+    SQ_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+    uint64_t *order_i = nullptr, *order_j = nullptr;
+    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, side->s>>>(pairs, P, P_dev, n, 1, rc);
+    SQ_LAUNCHED("gate_order_keys_kernel");
+    rc_ = radix_sort_u64(rc, rd, P, P_dev, 32, bits, ws + L.radix_j, sort_scratch, side->s, &order_j, "sort_gate_j");
+    if (rc_ != SUBQUAD_OK) return rc_;
+    SQ_HIP(hipEventRecord(side->done, side->s));
     gate_sorted_init_kernel<<<1, 64, 0, st>>>(flags);
     SQ_LAUNCHED("gate_sorted_init_kernel");
     gate_sorted_check_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, P_dev, n, flags);
@@ -896,15 +913,9 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, const int64_t *P_de
     SQ_LAUNCHED("gate_order_keys_kernel");
     // With no records to sort (pairs already in order) the sort writes nothing and ra keeps
     // the natural order, which is then the one used; otherwise its result is.
-    uint64_t *order_i = nullptr, *order_j = nullptr;
-    int rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, L.total - L.radix, st, &order_i,
-                             "sort_gate_i");
+    rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, sort_scratch, st, &order_i, "sort_gate_i");
     if (rc_ != SUBQUAD_OK) return rc_;
-    gate_order_keys_kernel<<<(unsigned)blocks, 256, 0, st>>>(pairs, P, P_dev, n, 1, rc);
-    SQ_LAUNCHED("gate_order_keys_kernel");
-    rc_ = radix_sort_u64(rc, rd, P, P_dev, 32, bits, ws + L.radix, L.total - L.radix, st, &order_j, "sort_gate_j");
-    if (rc_ != SUBQUAD_OK) return rc_;
-    o = GateOrders{ra, order_i, order_j, flags};
+    o = GateOrders{ra, order_i, order_j, flags, side->done};
     return SUBQUAD_OK;
 }
 
