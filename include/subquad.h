@@ -11,12 +11,19 @@
  *
  * Conventions shared by every entry point
  *   - Every array argument is DEVICE memory on the current HIP device unless it is marked
- *     "host".  The caller owns all memory and the library keeps no state between calls.
+ *     "host".  The caller owns all memory and the library keeps no data between calls
+ *     (it keeps a second stream per device and host thread, see below, and the static
+ *     array of the allocation-free alignment entry point).
  *     Entry points that take a workspace allocate nothing; subquad_check_seqs and
  *     subquad_align_batch (the variant without a workspace) take a small stream-ordered
  *     allocation (hipMallocAsync) and release it before returning.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it and the
- *     call returns without waiting, except where a host output is documented.
+ *     call returns without waiting, except where a host output is documented.  The gate
+ *     backward and training calls run one independent part (the pairs' order by j) on a
+ *     second stream the library creates once per device and host thread (non-blocking,
+ *     default priority): forked from `stream` by an event and joined back to it before the
+ *     call returns, so all of a call's work stays ordered on `stream`, and a graph captured
+ *     from `stream` holds it as a parallel branch.
  *   - Sequences are rows of `stride` bytes: residue codes 0..19 in the order
  *     ACDEFGHIKLMNPQRSTVWY, any value past the row's length (pad 0xFF by convention).
  *     `lens[i]` is the length of row i.
