@@ -913,7 +913,8 @@ static int gate_pair_orders(const int32_t *pairs, int64_t P, const int64_t *P_de
     SQ_LAUNCHED("gate_order_keys_kernel");
     // With no records to sort (pairs already in order) the sort writes nothing and ra keeps
     // the natural order, which is then the one used; otherwise its result is.
-    rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, sort_scratch, st, &order_i, "sort_gate_i");
+    rc_ = radix_sort_u64(ra, rb, P, flags + 1, 32, bits, ws + L.radix, sort_scratch, st, &order_i, "sort_gate_i",
+                         true);
     if (rc_ != SUBQUAD_OK) return rc_;
     o = GateOrders{ra, order_i, order_j, flags, side->done};
     return SUBQUAD_OK;

@@ -17,9 +17,11 @@ size_t radix_scratch_bytes(int64_t n_cap);
 // Stable sort of records [0, n) of `a` by bits [lo_bit, lo_bit + key_bits) using `b` as the
 // second buffer.  n = n_cap, or min(*n_dev, n_cap) when n_dev is non-null (read on the
 // device, so the call never synchronises).  *result receives a or b: the sorted buffer.
+// few_live: the device count is expected to be zero or small against a large capacity, so
+// the passes launch few blocks that loop over the tiles (cheap when empty, slower when full).
 int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev, int lo_bit,
                    int key_bits, void *scratch, size_t scratch_bytes, hipStream_t st,
-                   uint64_t **result, const char *tag = "radix");
+                   uint64_t **result, const char *tag = "radix", bool few_live = false);
 
 // In-place exclusive prefix sum of `count` 32-bit values (sum must fit in 32 bits).
 size_t scan_scratch_bytes(int64_t count);

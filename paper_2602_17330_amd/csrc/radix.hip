@@ -291,16 +291,12 @@ __device__ __forceinline__ int64_t live_count(int64_t n_cap, const int64_t *n_de
     return v < n_cap ? (v < 0 ? 0 : v) : n_cap;
 }
 
-__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_t *__restrict__ in, int64_t n_cap,
-                                                                   const int64_t *__restrict__ n_dev, int shift,
-                                                                   uint32_t dmask, uint32_t *__restrict__ hist,
-                                                                   int64_t nblocks) {
-    __shared__ uint32_t h[kRadixBuckets];
-    const int64_t n = live_count(n_cap, n_dev);
-    if (n_dev && n == 0) return;  // no records: the scan and the scatter skip this pass too
-    h[threadIdx.x] = 0;
+// One tile's digit counts into column tb of hist (zero past the live records).
+__device__ __forceinline__ void radix_hist_tile(const uint64_t *__restrict__ in, int64_t n, int shift, uint32_t dmask,
+                                                uint32_t *__restrict__ hist, int64_t nblocks, int64_t tb, uint32_t *h) {
+    h[threadIdx.x] = 0;  // (this thread read its counter of any previous tile already)
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = tb * kRadixTile;
     if (base < n) {
         // all loads in flight before any is used (an index past the end reads the last record
         // and is not counted)
@@ -317,23 +313,35 @@ __global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    hist[(int64_t)threadIdx.x * nblocks + tb] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
-    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n_cap, const int64_t *__restrict__ n_dev,
-    int shift, uint32_t dmask, const uint32_t *__restrict__ hist, int64_t nblocks) {
-    constexpr int kWaves = kRadixThreads / 64;
-    __shared__ uint32_t wc[kWaves][kRadixBuckets];
-    __shared__ uint32_t tile_off[kRadixBuckets];
-    __shared__ uint32_t gbase[kRadixBuckets];
-    __shared__ uint32_t wt[4];
-    __shared__ uint64_t stage[kRadixTile];
-
+// LOOP (the few-live form): blocks take tiles blockIdx.x, blockIdx.x + gridDim.x, ...;
+// otherwise one tile per block.  Every tile's column is written, zero past the live records.
+template <bool LOOP>
+__global__ __launch_bounds__(kRadixThreads) void radix_hist_kernel(const uint64_t *__restrict__ in, int64_t n_cap,
+                                                                   const int64_t *__restrict__ n_dev, int shift,
+                                                                   uint32_t dmask, uint32_t *__restrict__ hist,
+                                                                   int64_t nblocks) {
+    __shared__ uint32_t h[kRadixBuckets];
     const int64_t n = live_count(n_cap, n_dev);
-    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
-    if (tile0 >= n) return;  // whole block
+    if (n_dev && n == 0) return;  // no records: the scan and the scatter skip this pass too
+    if (!LOOP) {
+        radix_hist_tile(in, n, shift, dmask, hist, nblocks, blockIdx.x, h);
+        return;
+    }
+    for (int64_t tb = blockIdx.x; tb < nblocks; tb += gridDim.x) radix_hist_tile(in, n, shift, dmask, hist, nblocks, tb, h);
+}
+
+// One tile of the scatter (the block's LDS passed in); tile0 < n.
+__device__ __forceinline__ void radix_scatter_tile(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
+                                                   int64_t n, int shift, uint32_t dmask,
+                                                   const uint32_t *__restrict__ hist, int64_t nblocks, int64_t tb,
+                                                   uint32_t (*wc)[kRadixBuckets], uint32_t *tile_off, uint32_t *gbase,
+                                                   uint32_t *wt, uint64_t *stage) {
+    constexpr int kWaves = kRadixThreads / 64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t tile0 = tb * kRadixTile;
     for (int k = t; k < kWaves * kRadixBuckets; k += kRadixThreads) (&wc[0][0])[k] = 0;
     __syncthreads();
 
@@ -348,7 +356,7 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
         const int64_t idx = base + (int64_t)k * 64 + lane;
         rec[k] = in[idx < n ? idx : n - 1];
     }
-    const uint32_t my_base = hist[(int64_t)t * nblocks + blockIdx.x];  // kRadixThreads == kRadixBuckets
+    const uint32_t my_base = hist[(int64_t)t * nblocks + tb];  // kRadixThreads == kRadixBuckets
 #pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
         int64_t idx = base + (int64_t)k * 64 + lane;
@@ -407,6 +415,31 @@ __global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
     }
 }
 
+// LOOP (the few-live form): blocks take tiles blockIdx.x, blockIdx.x + gridDim.x, ...;
+// otherwise one tile per block.
+template <bool LOOP>
+__global__ __launch_bounds__(kRadixThreads) void radix_scatter_kernel(
+    const uint64_t *__restrict__ in, uint64_t *__restrict__ out, int64_t n_cap, const int64_t *__restrict__ n_dev,
+    int shift, uint32_t dmask, const uint32_t *__restrict__ hist, int64_t nblocks) {
+    constexpr int kWaves = kRadixThreads / 64;
+    __shared__ uint32_t wc[kWaves][kRadixBuckets];
+    __shared__ uint32_t tile_off[kRadixBuckets];
+    __shared__ uint32_t gbase[kRadixBuckets];
+    __shared__ uint32_t wt[4];
+    __shared__ uint64_t stage[kRadixTile];
+    const int64_t n = live_count(n_cap, n_dev);
+    if (!LOOP) {
+        if ((int64_t)blockIdx.x * kRadixTile >= n) return;  // whole block
+        radix_scatter_tile(in, out, n, shift, dmask, hist, nblocks, blockIdx.x, wc, tile_off, gbase, wt, stage);
+        return;
+    }
+    for (int64_t tb = blockIdx.x; tb < nblocks; tb += gridDim.x) {
+        if (tb * kRadixTile >= n) break;  // this tile and every later one hold no live record
+        radix_scatter_tile(in, out, n, shift, dmask, hist, nblocks, tb, wc, tile_off, gbase, wt, stage);
+        __syncthreads();  // the LDS counters and the staged tile are reused by the next tile
+    }
+}
+
 size_t radix_scratch_bytes(int64_t n_cap) {
     int64_t nblocks = std::max<int64_t>(1, ceil_div(n_cap, kRadixTile));
     int64_t hist = nblocks * kRadixBuckets;
@@ -414,13 +447,26 @@ size_t radix_scratch_bytes(int64_t n_cap) {
 }
 
 int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev, int lo_bit, int key_bits,
-                   void *scratch, size_t scratch_bytes, hipStream_t st, uint64_t **result, const char *tag) {
+                   void *scratch, size_t scratch_bytes, hipStream_t st, uint64_t **result, const char *tag,
+                   bool few_live) {
     const std::string hist_name = std::string(tag) + "_hist", scan_name = std::string(tag) + "_scan",
                       scatter_name = std::string(tag) + "_scatter";
     *result = a;
     if (n_cap <= 1 || key_bits <= 0) return SUBQUAD_OK;
     SQ_REQUIRE(scratch_bytes >= radix_scratch_bytes(n_cap), SUBQUAD_ERR_WORKSPACE, "radix scratch too small");
-    const int64_t nblocks = ceil_div(n_cap, kRadixTile);
+    const int64_t nblocks = ceil_div(n_cap, kRadixTile);  // tiles
+    // one tile per block, unless few records are expected to be live (the device count is
+    // usually zero): then at most as many blocks as the chip holds at once, striding by the
+    // grid, so that an empty pass dispatches few blocks whatever the capacity (a full pass in
+    // this form is slower: its tiles in flight spread further apart than dispatch order keeps
+    // them, and their scattered writes lose locality)
+    int64_t grid_h = nblocks, grid_s = nblocks;
+    if (few_live) {
+        grid_h = std::min<int64_t>(
+            nblocks, (int64_t)resident_blocks_per_cu((const void *)radix_hist_kernel<true>) * device_cus());
+        grid_s = std::min<int64_t>(
+            nblocks, (int64_t)resident_blocks_per_cu((const void *)radix_scatter_kernel<true>) * device_cus());
+    }
     const int64_t hist_n = nblocks * kRadixBuckets;
     SQ_REQUIRE(n_cap < (int64_t(1) << 32), SUBQUAD_ERR_ARG, "radix sort limited to 2^32 records");
     uint32_t *hist = static_cast<uint32_t *>(scratch);
@@ -432,8 +478,12 @@ int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev
         const uint32_t dmask = (1u << bits) - 1u;
         {
             ProfScope prof(hist_name.c_str(), st);
-            radix_hist_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask, hist,
-                                                                           nblocks);
+            if (few_live)
+                radix_hist_kernel<true><<<(unsigned)grid_h, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask,
+                                                                                hist, nblocks);
+            else
+                radix_hist_kernel<false><<<(unsigned)grid_h, kRadixThreads, 0, st>>>(src, n_cap, n_dev, shift, dmask,
+                                                                                 hist, nblocks);
         }
         SQ_LAUNCHED("radix_hist_kernel");
         int rc;
@@ -444,8 +494,12 @@ int radix_sort_u64(uint64_t *a, uint64_t *b, int64_t n_cap, const int64_t *n_dev
         if (rc != SUBQUAD_OK) return rc;
         {
             ProfScope prof(scatter_name.c_str(), st);
-            radix_scatter_kernel<<<(unsigned)nblocks, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift, dmask,
-                                                                              hist, nblocks);
+            if (few_live)
+                radix_scatter_kernel<true><<<(unsigned)grid_s, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift,
+                                                                                    dmask, hist, nblocks);
+            else
+                radix_scatter_kernel<false><<<(unsigned)grid_s, kRadixThreads, 0, st>>>(src, dst, n_cap, n_dev, shift,
+                                                                                     dmask, hist, nblocks);
         }
         SQ_LAUNCHED("radix_scatter_kernel");
         std::swap(src, dst);

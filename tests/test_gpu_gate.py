@@ -499,3 +499,39 @@ def test_gate_train_set_rep1m_2p20_writes_demb(sorted_pairs):
     assert not g2[4][torch.from_numpy(~touched).cuda()].any()
     for a, b in zip(g1, g2):
         assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(a.abs().max()))
+
+
+def test_gate_train_set_8m_shuffled_pairs_sorted_by_i():
+    """8M pairs of the 1M-sequence workload (about 2,000 sort tiles: more than the chip holds
+    blocks of the i sort at once, so that sort loops over its tiles), shuffled, against the
+    same pairs in order of i (whose i sort is empty): fused values equal pair by pair, the
+    loss and every gradient equal to summation order."""
+    rep = workload("rep1m")
+    n = rep.n
+    pairs = synth.random_pairs(n, 9_700_000, 31, family=rep.family, same_frac=0.5)  # (duplicates dropped)
+    P = pairs.shape[0]
+    assert P >= 8_000_000
+    rng = np.random.default_rng(31)
+    align = rng.integers(0, 120, P).astype(np.int32)
+    W1, b1, w2, b2 = synth.gate_params(64)
+    S = synth.load_blosum62()
+    c = dict(emb=synth.embeddings(rep.seqs, rep.lens, 128), lens=rep.lens, vgene=rep.vgene,
+             self_scores=osw.self_scores(rep.seqs, rep.lens, S), pairs=pairs, align=align,
+             W1=W1, b1=b1, w2=w2, b2=b2)
+    perm = rng.permutation(P)
+    cu = dict(c, pairs=np.ascontiguousarray(pairs[perm]), align=np.ascontiguousarray(align[perm]))
+    lab = dev(rep.family.astype(np.int32))
+    say(f"gate train set P={P}: pairs in order of i, then shuffled")
+    runs = []
+    for case in (c, cu):
+        args = gpu_args(case)
+        g0 = tuple(torch.zeros_like(w) for w in args[6:]) + (torch.full_like(args[0], float("nan")),)
+        f, loss, g = sq.api.gate_train(*args, lab, 0.5, grads=g0, set_demb=True)
+        torch.cuda.synchronize()
+        runs.append((f[:P].cpu().numpy(), loss.item(), [x.cpu() for x in g]))
+    (f_s, l_s, g_s), (f_u, l_u, g_u) = runs
+    assert np.array_equal(f_s[perm], f_u)
+    assert abs(l_s - l_u) <= 1e-12 * abs(l_s)
+    assert not torch.isnan(g_u[4]).any()
+    for a, b in zip(g_s, g_u):
+        assert torch.allclose(a, b, rtol=1e-5, atol=1e-7 * float(a.abs().max()))
