@@ -575,29 +575,58 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
 
 // Long runs (more than kSmallRun records): one thread per (run, x < y) pair of records, the
 // long runs' pairs flattened by the prefix sum of their pair counts; k-th pair of a run:
-// y = the largest y with y(y-1)/2 <= k, x = k - y(y-1)/2.  A block's window of consecutive
-// pair indices spans few runs (a long run has at least kSmallRun (kSmallRun + 1) / 2 pairs):
-// one thread finds the window's first run in the global prefix, the window's runs and
-// offsets are staged in LDS, and every thread finds its run there.  A run's pairs are
-// consecutive, so its members' class-id rows are read from the cache by the threads that
-// share them.
-constexpr int kEmitWin = 64;  // runs staged per window
+// y = the largest y with y(y-1)/2 <= k, x = k - y(y-1)/2.  A window of kEmitWin runs always
+// covers a round's pairs (a long run has at least kSmallRun (kSmallRun + 1) / 2 of them).
+// With at most one round of pairs per block, block b takes pairs b blockDim.x + threadIdx.x:
+// one thread finds the block's first run in the global prefix, the window after it is
+// staged in LDS and every thread finds its run there.  With more pairs each block takes one
+// contiguous range in rounds: its first run is searched once and each next round's first
+// run is found in the staged window (no round waits on the global prefix), and kept keys
+// collect in LDS and leave in batches (one global atomic per batch rather than per round:
+// atomics on one address serialise).  A run's pairs are consecutive, so its members'
+// class-id rows are read from the cache by the threads that share them.
+constexpr int kEmitWin = 64;         // runs staged per window
+
+// Pair t of the flattened long runs, given the staged window of runs (t falls in one of
+// them): its run by bisection over the staged offsets, its (x, y) by the triangular root,
+// then the first-band test.
+__device__ __forceinline__ bool long_pair_test(uint64_t t, const uint64_t *wpoff, const uint64_t *wrun,
+                                               const uint64_t *__restrict__ srec, uint32_t n32, int32_t b,
+                                               const uint32_t *__restrict__ C, int64_t &i, int64_t &j) {
+    int lo = 0, hi = kEmitWin - 1;  // last staged run with poff <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (wpoff[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t start = wrun[lo] >> 32;
+    const uint64_t k = t - wpoff[lo];
+    uint64_t y = (uint64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
+    while (y * (y - 1) / 2 > k) --y;
+    while ((y + 1) * y / 2 <= k) ++y;
+    const uint64_t x = k - y * (y - 1) / 2;
+    const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
+    return pair_first_here(la, lb, n32, b, C, i, j);
+}
+constexpr int kEmitLongBuf = 4096;   // kept keys buffered per block
 __global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
     const uint64_t *__restrict__ srec, int64_t n, int32_t b, const uint32_t *__restrict__ C, int nb,
     const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
     static_assert((kSmallRun + 1) * kSmallRun / 2 * (kEmitWin - 1) >= 1024, "a window may span more runs");
-    __shared__ uint32_t lcount;
+    __shared__ uint32_t kn;
     __shared__ unsigned long long gbase;
     __shared__ uint64_t wrun[kEmitWin], wpoff[kEmitWin];
+    __shared__ uint64_t kbuf[kEmitLongBuf];
     __shared__ int64_t wfirst;
     const int64_t nruns = (int64_t)counters[2];
     const uint64_t visits = (uint64_t)counters[1];
     const uint32_t n32 = (uint32_t)n;
-    // block-uniform trip count: every thread reaches block_slot in every round
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < visits; base += (uint64_t)gridDim.x * blockDim.x) {
+    if (visits <= (uint64_t)gridDim.x * blockDim.x) {  // (uniform) at most one round per block
+        const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if ((uint64_t)blockIdx.x * blockDim.x >= visits) return;  // (the whole block)
         if (threadIdx.x == 0) {
-            int64_t lo = 0, hi = nruns - 1;  // last run with poff <= base
+            int64_t lo = 0, hi = nruns - 1;  // last run with poff <= the block's first pair
+            const uint64_t base = (uint64_t)blockIdx.x * blockDim.x;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
                 if (poff[mid] <= base) lo = mid; else hi = mid - 1;
@@ -605,6 +634,48 @@ __global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
             wfirst = lo;
         }
         __syncthreads();
+        for (int k = threadIdx.x; k < kEmitWin; k += blockDim.x) {
+            const int64_t q = wfirst + k;
+            wpoff[k] = q < nruns ? poff[q] : ~0ull;
+            wrun[k] = q < nruns ? runs[q] : 0ull;
+        }
+        __syncthreads();
+        bool want = false;
+        int64_t i = 0, j = 0;
+        if (t < visits) want = long_pair_test(t, wpoff, wrun, srec, n32, b, C, i, j);
+        const unsigned long long slot = block_slot(count, want, &kn, &gbase);  // (synchronises the block)
+        if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+        return;
+    }
+    // many pairs: equal contiguous ranges
+    const uint64_t per = (visits + gridDim.x - 1) / gridDim.x;
+    const uint64_t v0 = (uint64_t)blockIdx.x * per, v1 = min(visits, v0 + per);
+    if (v0 >= v1) return;  // (the whole block) no pairs left for it
+    // kept keys collect in LDS and leave in batches: one global atomic and contiguous stores
+    // per batch (all threads call it)
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t cnt = kn;
+        if (threadIdx.x == 0 && cnt) gbase = atomicAdd(count, (unsigned long long)cnt);
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < cnt; x += blockDim.x)
+            if ((int64_t)(gbase + x) < cap) pkeys[gbase + x] = kbuf[x];
+        __syncthreads();
+        if (threadIdx.x == 0) kn = 0u;
+        __syncthreads();
+    };
+    if (threadIdx.x == 0) {
+        kn = 0u;
+        int64_t lo = 0, hi = nruns - 1;  // last run with poff <= v0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (poff[mid] <= v0) lo = mid; else hi = mid - 1;
+        }
+        wfirst = lo;
+    }
+    __syncthreads();
+    // block-uniform trip count: every thread reaches every round's barriers
+    for (uint64_t base = v0; base < v1; base += blockDim.x) {
         const int64_t first = wfirst;
         for (int k = threadIdx.x; k < kEmitWin; k += blockDim.x) {
             const int64_t q = first + k;
@@ -615,25 +686,22 @@ __global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
         const uint64_t t = base + threadIdx.x;
         bool want = false;
         int64_t i = 0, j = 0;
-        if (t < visits) {
-            int lo = 0, hi = kEmitWin - 1;  // last staged run with poff <= t
+        if (t < v1) want = long_pair_test(t, wpoff, wrun, srec, n32, b, C, i, j);
+        if (want) kbuf[atomicAdd(&kn, 1u)] = ((uint64_t)i << nb) | (uint64_t)j;
+        __syncthreads();  // every thread is done with the staged runs and the buffer count
+        if (threadIdx.x == 0) {  // the next round's first run, among the staged ones
+            const uint64_t next = base + blockDim.x;
+            int lo = 0, hi = kEmitWin - 1;
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (wpoff[mid] <= t) lo = mid; else hi = mid - 1;
+                if (wpoff[mid] <= next) lo = mid; else hi = mid - 1;
             }
-            const uint64_t run = wrun[lo];
-            const uint64_t start = run >> 32;
-            const uint64_t k = t - wpoff[lo];
-            uint64_t y = (uint64_t)((1.0f + sqrtf(1.0f + 8.0f * (float)k)) * 0.5f);
-            while (y * (y - 1) / 2 > k) --y;
-            while ((y + 1) * y / 2 <= k) ++y;
-            const uint64_t x = k - y * (y - 1) / 2;
-            const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
-            want = pair_first_here(la, lb, n32, b, C, i, j);
+            wfirst = first + lo;
         }
-        const unsigned long long slot = block_slot(count, want, &lcount, &gbase);  // (synchronises the block)
-        if (want && (int64_t)slot < cap) pkeys[slot] = ((uint64_t)i << nb) | (uint64_t)j;
+        __syncthreads();  // wfirst is set and the staged runs are free again
+        if (kn > kEmitLongBuf - blockDim.x) flush();  // (uniform) room for one more round
     }
+    flush();
 }
 
 __global__ void lsh_init_kernel(unsigned long long *count) {
