@@ -585,7 +585,8 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
 // collect in LDS and leave in batches (one global atomic per batch rather than per round:
 // atomics on one address serialise).  A run's pairs are consecutive, so its members'
 // class-id rows are read from the cache by the threads that share them.
-constexpr int kEmitWin = 64;         // runs staged per window
+constexpr int kEmitWin = 64;        // runs staged per window
+constexpr int kEmitLongBuf = 4096;  // kept keys of long runs buffered per block
 
 // Pair t of the flattened long runs, given the staged window of runs (t falls in one of
 // them): its run by bisection over the staged offsets, its (x, y) by the triangular root,
@@ -607,7 +608,7 @@ __device__ __forceinline__ bool long_pair_test(uint64_t t, const uint64_t *wpoff
     const uint32_t la = (uint32_t)srec[start + x], lb = (uint32_t)srec[start + y];
     return pair_first_here(la, lb, n32, b, C, i, j);
 }
-constexpr int kEmitLongBuf = 4096;   // kept keys buffered per block
+
 __global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
     const uint64_t *__restrict__ srec, int64_t n, int32_t b, const uint32_t *__restrict__ C, int nb,
     const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
