@@ -584,7 +584,9 @@ __global__ __launch_bounds__(kEmitThreads) void lsh_emit_small_kernel(
 // run is found in the staged window (no round waits on the global prefix), and kept keys
 // collect in LDS and leave in batches (one global atomic per batch rather than per round:
 // atomics on one address serialise).  A run's pairs are consecutive, so its members'
-// class-id rows are read from the cache by the threads that share them.
+// class-id rows are read from the cache by the threads that share them.  The kernel waits on
+// loads: it is held to six waves per SIMD (80 registers) rather than the five its registers
+// would otherwise allow.
 constexpr int kEmitWin = 64;        // runs staged per window
 constexpr int kEmitLongBuf = 4096;  // kept keys of long runs buffered per block
 
@@ -609,7 +611,7 @@ __device__ __forceinline__ bool long_pair_test(uint64_t t, const uint64_t *wpoff
     return pair_first_here(la, lb, n32, b, C, i, j);
 }
 
-__global__ __launch_bounds__(1024) void lsh_emit_long_kernel(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void lsh_emit_long_kernel(
     const uint64_t *__restrict__ srec, int64_t n, int32_t b, const uint32_t *__restrict__ C, int nb,
     const uint64_t *__restrict__ runs, const uint64_t *__restrict__ poff, const unsigned long long *__restrict__ counters,
     uint64_t *__restrict__ pkeys, int64_t cap, unsigned long long *__restrict__ count) {
