@@ -23,7 +23,8 @@
  *     second stream the library creates once per device and host thread (non-blocking,
  *     default priority): forked from `stream` by an event and joined back to it before the
  *     call returns, so all of a call's work stays ordered on `stream`, and a graph captured
- *     from `stream` holds it as a parallel branch.
+ *     from `stream` holds it as a parallel branch.  The first such call on a device and host
+ *     thread creates that stream and its events: make it outside a graph capture.
  *   - Sequences are rows of `stride` bytes: residue codes 0..19 in the order
  *     ACDEFGHIKLMNPQRSTVWY, any value past the row's length (pad 0xFF by convention).
  *     `lens[i]` is the length of row i.
